@@ -1,0 +1,191 @@
+/*
+ * hom4d.h -- C ABI of the MI355X (gfx950) two-electron split-step propagator.
+ *
+ * The library advances the exact two-electron wavefunction Psi(x1, y1, x2, y2)
+ * of a Hall-edge Hong-Ou-Mandel interferometer on a 4D grid, as in
+ * L. Bellentani, P. Bordone, X. Oriols, A. Bertoni, arXiv 1903.02581:
+ *   - Sec. II.C, Eq. (evoloperat) and Appendix A: split-step Fourier method for
+ *     two particles in a perpendicular field, kinetic terms diagonal in mixed
+ *     real/reciprocal representations, potentials diagonal in 4D real space;
+ *   - Sec. III.B, Eq. (coulomb) / Eq. (screenedCoulomb): the two-body term;
+ *   - Sec. III, Eq. (p_bunching): region-resolved (bunching) probabilities;
+ *   - Sec. III.C, Eq. (reduced_density): spatial entanglement of 1D slices.
+ *
+ * Conventions (readings where the paper is silent, fixed here):
+ *   - units nm, fs, meV, tesla; electron charge -e; gauge A = (-B y, 0), so the
+ *     x kinetic term is (hbar k_x - e B y)^2 / 2m*, diagonal in (k_x, y), and
+ *     the y kinetic term hbar^2 k_y^2 / 2m*, diagonal in k_y;
+ *   - grids x_i = -Lx/2 + i Lx/nx, y_j = -Ly/2 + j Ly/ny, periodic; forward DFT
+ *     exp(-i k x); wave number index m >= n/2 maps to m - n (Nyquist = -pi/dx);
+ *   - one step is the symmetric product S(dt) = X(dt/2) V(dt/2) Y(dt) V(dt/2) X(dt/2)
+ *     with V = V(r1) + V(r2) + V12(r1, r2); consecutive X halves are merged
+ *     inside one hom4d_step call, which always ends on a whole step;
+ *   - V12 = C e^2 / (4 pi eps0 eps_r sqrt(|r1 - r2|^2 + d^2)), times
+ *     exp(-|r1 - r2| / sigma_c) when screen_nm = sigma_c > 0;
+ *   - canonical state layout: row-major [x1][y1][x2][y2] of interleaved
+ *     complex (re, im); the device state uses the same layout, in complex128
+ *     (HOM4D_FP64) or complex64 (HOM4D_MIXED) storage.  All arithmetic --
+ *     transforms, phase products, potential angles, reductions -- is FP64 in
+ *     both precisions; HOM4D_MIXED only rounds the stored state to FP32.
+ *
+ * Ownership: host arrays are owned by the caller and copied during the call.
+ * The state buffer (and the adjoint and checkpoint buffers) are device memory
+ * owned by the caller (typically torch tensors); the library keeps only the
+ * pointer while bound.  The handle owns O(nx*ny) tables and small reduction
+ * scratch.  All device work is enqueued on the HIP stream given at create
+ * time; calls that return host results synchronise that stream.
+ *
+ * Errors: every call returns 0 (HOM4D_OK) or a negative HOM4D_E* code and
+ * never throws across the ABI.  hom4d_last_error() gives a thread-local
+ * detail string for the last failing call on this thread.
+ */
+#ifndef HOM4D_H
+#define HOM4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOM4D_OK 0
+#define HOM4D_EINVAL (-1)      /* bad argument: size, pointer, flag, step count */
+#define HOM4D_EUNBOUND (-2)    /* no state buffer bound */
+#define HOM4D_ESTATE (-3)      /* call out of order (e.g. backward without a recorded forward) */
+#define HOM4D_ENOMEM (-4)      /* caller-provided buffer too small, or a table allocation failed */
+#define HOM4D_EHIP (-5)        /* HIP runtime error; detail in hom4d_last_error() */
+#define HOM4D_ENONFINITE (-6)  /* the state holds a NaN or Inf */
+#define HOM4D_ENORMDRIFT (-7)  /* |norm - 1| above the watchdog tolerance */
+
+#define HOM4D_FP64 0           /* complex128 state */
+#define HOM4D_MIXED 1          /* complex64 state, FP64 arithmetic */
+
+#define HOM4D_COULOMB_TABLE 0  /* V12 phase from a device table over (x1-x2, y1-y2) */
+#define HOM4D_COULOMB_DIRECT 1 /* V12 angle evaluated per 4D point on the fly */
+
+typedef struct hom4d hom4d;
+
+/* Problem definition.  nx, ny: grid points per electron, each of the form
+ * 2^a 3^b in {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256}.  Lengths in nm,
+ * dt in fs, B in tesla (Appendix A: field along +z), soft_nm = d and
+ * coulomb_c = C of Eq. (coulomb) (C = 0 switches the two-body term off),
+ * screen_nm = sigma_c of Eq. (screenedCoulomb) (0 = unscreened). */
+typedef struct {
+    int32_t nx, ny;
+    int32_t precision;      /* HOM4D_FP64 or HOM4D_MIXED */
+    int32_t coulomb_mode;   /* HOM4D_COULOMB_TABLE or HOM4D_COULOMB_DIRECT */
+    double lx_nm, ly_nm;
+    double mstar_rel;       /* m* / m_e (GaAs: 0.067) */
+    double eps_r;           /* relative permittivity (GaAs: 12.9) */
+    double b_tesla;
+    double dt_fs;
+    double soft_nm;
+    double coulomb_c;
+    double screen_nm;
+} hom4d_cfg;
+
+/* Region-resolved probabilities of Eq. (p_bunching) as raw grid sums of
+ * |Psi|^2 weighted by w(r1), w(r2) (T) and 1 - w (B); p_b = p_tt + p_bb,
+ * p_ab = p_tb + p_bt; norm = sum |Psi|^2.  step counts whole steps taken
+ * since the last init/load. */
+typedef struct {
+    double norm, p_tt, p_tb, p_bt, p_bb, p_b, p_ab;
+    int64_t step;
+} hom4d_obs;
+
+/* Validate cfg, build the phase and twiddle tables and upload them.
+ * hip_stream: a hipStream_t (NULL = the null stream).  On success *out owns
+ * the handle.  EINVAL on an unsupported size or a non-positive length / dt /
+ * mass / permittivity / softening; EHIP if no device is usable. */
+int hom4d_create(const hom4d_cfg* cfg, void* hip_stream, hom4d** out);
+
+/* Release the handle and its tables (not the bound caller buffers). */
+int hom4d_destroy(hom4d* h);
+
+/* Checks cfg without touching the GPU; returns HOM4D_OK or HOM4D_EINVAL. */
+int hom4d_validate_cfg(const hom4d_cfg* cfg);
+
+/* Bytes of one device state buffer for cfg: (nx*ny)^2 * (16 or 8); 0 if cfg is invalid. */
+size_t hom4d_state_bytes(const hom4d_cfg* cfg);
+
+/* Bind the caller-owned device state buffer (hom4d_state_bytes bytes, 16-byte
+ * aligned).  Rebinding discards any gradient recording. */
+int hom4d_bind_state(hom4d* h, void* d_psi);
+
+/* External potential V(x, y) in meV, host row-major [nx][ny] FP64, the same
+ * for both electrons.  Rebuilds the potential phase tables. */
+int hom4d_set_potential(hom4d* h, const double* v_meV);
+
+/* Change B (tesla); rebuilds the x kinetic phase tables. */
+int hom4d_set_field(hom4d* h, double b_tesla);
+
+/* Initial state of Sec. II.C Eq. (twopstate) from two single-electron
+ * orbitals, host row-major [nx][ny] interleaved complex128:
+ *   sym = -1: psi_a(r1) psi_b(r2) - psi_a(r2) psi_b(r1) (Slater determinant),
+ *   sym = +1: the symmetric combination, sym = 0: the product psi_a(r1) psi_b(r2);
+ * then normalised so that the 4D grid sum of |Psi|^2 is 1 (FP64 norm).
+ * EINVAL on another sym or a zero-norm combination.  Resets the step count. */
+int hom4d_init_state(hom4d* h, const double* psi_a, const double* psi_b, int32_t sym);
+
+/* Copy a canonical complex128 state in/out (host, (nx*ny)^2 complex values).
+ * load resets the step count; in MIXED the values are rounded to complex64. */
+int hom4d_load_state(hom4d* h, const double* psi4d);
+int hom4d_store_state(hom4d* h, double* psi4d);
+
+/* Advance the bound state by n >= 0 whole steps S(dt); asynchronous on the
+ * stream.  While a gradient recording is open, also stores the checkpoints. */
+int hom4d_step(hom4d* h, int64_t n);
+
+/* Region-resolved probabilities of the bound state for the top-region weight
+ * table w_top (host [nx][ny] FP64, values in [0, 1]).  Synchronises.
+ * Returns ENONFINITE if the state holds a NaN/Inf, ENORMDRIFT if
+ * |norm - 1| > norm_tol (set with hom4d_set_norm_tol; default 1e-6);
+ * *out is filled in either case. */
+int hom4d_observables(hom4d* h, const double* w_top, hom4d_obs* out);
+int hom4d_set_norm_tol(hom4d* h, double tol);
+
+/* Von Neumann entropy of the slice phi(a, b) = Psi(ix1[a], jy1, ix2[b], jy2)
+ * (Sec. III.C): phi is renormalised, rho = phi phi^dagger, S = -Tr rho ln rho
+ * (natural log).  1 <= n1, n2 <= 256; indices in range.  Synchronises. */
+int hom4d_entanglement(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1,
+                       const int32_t* ix2, int32_t n2, int32_t jy2, double* s_out);
+
+/* Gather the (n1 x n2) slice above into host memory (interleaved complex128),
+ * unnormalised.  Synchronises. */
+int hom4d_gather_slice(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1,
+                       const int32_t* ix2, int32_t n2, int32_t jy2, double* out);
+
+/* Start recording a forward run for the adjoint.  The current bound state is
+ * checkpoint 0; every ckpt_every steps taken by later hom4d_step calls the
+ * state is copied into the caller-owned device pool (pool_bytes bytes, slots
+ * of hom4d_state_bytes).  hom4d_step returns ENOMEM when the next checkpoint
+ * would not fit. */
+int hom4d_grad_begin(hom4d* h, int32_t ckpt_every, void* d_pool, size_t pool_bytes);
+
+/* Reverse sweep for L = sum w_L |Psi_N|^2 with
+ * w_L = c[0] w1 w2 + c[1] w1 (1-w2) + c[2] (1-w1) w2 + c[3] (1-w1)(1-w2)
+ * (c = {1,0,0,1}: the bunching probability).  d_lambda: caller-owned device
+ * buffer of hom4d_state_bytes for the adjoint state.  The state and the
+ * adjoint are carried back together by S(-dt); at every checkpoint the state
+ * is replaced by the stored copy (bounds the reverse drift).  Outputs:
+ * *loss = L, dL_dV (host [nx][ny] FP64, derivative with respect to the
+ * potential table in 1/meV), *dL_dB (1/T).  On return the bound state holds
+ * checkpoint 0 and the recording is closed.  ESTATE without a recording. */
+int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs,
+                        void* d_lambda, double* loss, double* dL_dV, double* dL_dB);
+
+/* Abandon an open recording. */
+int hom4d_grad_end(hom4d* h);
+
+/* Static string for a status code. */
+const char* hom4d_strerror(int status);
+
+/* Thread-local detail of the last failing call on this thread ("" if none). */
+const char* hom4d_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOM4D_H */

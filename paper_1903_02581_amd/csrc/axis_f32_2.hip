@@ -1,0 +1,6 @@
+// Instantiations of the per-axis pass for float2 storage, 2 state(s) per pass.
+#include "axis_pass.hpp"
+
+namespace hom4d_impl {
+dev::AxisKernel pick_axis_f32_2(int axis, int n, int* t) { return dev::pick_axis<float2, 2>(axis, n, t); }
+}  // namespace hom4d_impl

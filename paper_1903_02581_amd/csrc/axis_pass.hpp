@@ -1,0 +1,396 @@
+// The per-axis pass kernel (template) and its device helpers; included by the
+// translation units that instantiate it for one storage type and state count.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dft_regs.hpp"
+#include "hom4d_internal.hpp"
+
+namespace hom4d_impl {
+namespace dev {
+using namespace hom4d_dev;
+
+template <class S>
+__device__ __forceinline__ double2 ld(const S* p);
+template <>
+__device__ __forceinline__ double2 ld<double2>(const double2* p) {
+    return *p;
+}
+template <>
+__device__ __forceinline__ double2 ld<float2>(const float2* p) {
+    const float2 f = *p;
+    return make_double2((double)f.x, (double)f.y);
+}
+template <class S>
+__device__ __forceinline__ void st(S* p, double2 v);
+template <>
+__device__ __forceinline__ void st<double2>(double2* p, double2 v) {
+    *p = v;
+}
+template <>
+__device__ __forceinline__ void st<float2>(float2* p, double2 v) {
+    *p = make_float2((float)v.x, (float)v.y);
+}
+
+__device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
+
+// Im(conj(l) * p)
+__device__ __forceinline__ double im_cl_p(double2 l, double2 p) { return fma(l.x, p.y, -l.y * p.x); }
+
+// theta - 2 pi * rint(theta / 2 pi), 2 pi split in three parts (Cody & Waite);
+// the first part has 9 significant bits, so q * c1 is exact for |q| < 2^44.
+__device__ __forceinline__ double reduce_2pi(double th) {
+    const double inv2pi = 0.15915494309189535;
+    const double c1 = 6.28125;
+    const double c2 = 0.001935307179586477;
+    const double c3 = -1.0033115225336665e-19;
+    const double q = rint(th * inv2pi);
+    return fma(-q, c3, fma(-q, c2, fma(-q, c1, th)));
+}
+
+// exp(-i tau (V(r1) + V(r2) + V12(r1 - r2)) / hbar), or its conjugate.
+__device__ __forceinline__ double2 vfactor(const PassArgs& a, int i1, int j1, int i2, int j2) {
+    double2 f;
+    if (!a.vdirect) {
+        f = cmul(a.a1[i1 * a.ny + j1], a.a1[i2 * a.ny + j2]);
+        if (a.ac) f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)]);
+        if (a.kconj) f = conjd(f);
+    } else {
+        double v = a.vtab[i1 * a.ny + j1] + a.vtab[i2 * a.ny + j2];
+        if (a.ck != 0.0) {
+            const double ddx = (double)(i1 - i2) * a.dx;
+            const double ddy = (double)(j1 - j2) * a.dy;
+            const double r2 = ddx * ddx + ddy * ddy;
+            double vc = a.ck / sqrt(r2 + a.soft2);
+            if (a.inv_screen > 0.0) vc *= exp(-sqrt(r2) * a.inv_screen);
+            v += vc;
+        }
+        const double th = reduce_2pi(a.vscale * v);  // vscale carries the sign of tau
+        double s, c;
+        sincos(th, &s, &c);
+        f = make_double2(c, -s);
+    }
+    return f;
+}
+
+// Sum over the block, valid in thread 0.  blockDim.x is a power of two.
+__device__ inline double block_sum(double v, double* red) {
+    const int tid = threadIdx.x;
+    const int nb = blockDim.x;
+    if (nb >= 64) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
+        if (tid == 0)
+            for (int w = 0; w < (nb >> 6); ++w) s += red[w];
+        return s;
+    }
+    __syncthreads();
+    red[tid] = v;
+    __syncthreads();
+    for (int o = nb >> 1; o >= 1; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    return tid == 0 ? red[0] : 0.0;
+}
+
+// Coordinates (i1, j1, i2, j2) of element m of a line along AXIS.
+template <int AXIS>
+__device__ __forceinline__ void elem_coord(int i1, int j1, int i2, int j2, int m, int* c) {
+    c[0] = i1;
+    c[1] = j1;
+    c[2] = i2;
+    c[3] = j2;
+    c[AXIS] = m;
+}
+
+template <class S, int AXIS, int N1, int N2, int T, int NST>
+__global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
+    constexpr int N = N1 * N2;
+    constexpr int E = N / T;
+    constexpr int JA = N2 / T;  // stage-A columns per thread
+    constexpr int IB = N1 / T;  // stage-B rows per thread
+    static_assert(N1 % T == 0 && N2 % T == 0, "t must divide both factors");
+    extern __shared__ double2 lds[];
+
+    const int W = a.W;
+    const int tid = threadIdx.x;
+    int t, cl;
+    if constexpr (AXIS == AX_Y2) {
+        t = tid % T;
+        cl = tid / T;
+    } else {
+        cl = tid % W;
+        t = tid / W;
+    }
+    const uint32_t line = blockIdx.x * (uint32_t)W + (uint32_t)cl;
+    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nxy = nx * ny;
+    int i1 = 0, j1 = 0, i2 = 0, j2 = 0;
+    int64_t base, sN;
+    if constexpr (AXIS == AX_X1) {
+        j1 = (int)(line / nxy);
+        i2 = (int)((line / ny) % nx);
+        j2 = (int)(line % ny);
+        base = line;
+        sN = (int64_t)ny * nxy;
+    } else if constexpr (AXIS == AX_Y1) {
+        i1 = (int)(line / nxy);
+        const uint32_t c = line % nxy;
+        i2 = (int)(c / ny);
+        j2 = (int)(c % ny);
+        base = (int64_t)i1 * ny * nxy + c;
+        sN = nxy;
+    } else if constexpr (AXIS == AX_X2) {
+        const uint32_t o = line / ny;
+        i1 = (int)(o / ny);
+        j1 = (int)(o % ny);
+        j2 = (int)(line % ny);
+        base = (int64_t)o * nxy + j2;
+        sN = ny;
+    } else {
+        i1 = (int)(line / nxy);
+        j1 = (int)((line / nx) % ny);
+        i2 = (int)(line % nx);
+        base = (int64_t)line * ny;
+        sN = 1;
+    }
+
+    S* ps[NST];
+    ps[0] = reinterpret_cast<S*>(a.psi) + base;
+    if constexpr (NST == 2) ps[1] = reinterpret_cast<S*>(a.lam) + base;
+
+    double2 v[NST][E];
+#pragma unroll
+    for (int jj = 0; jj < JA; ++jj) {
+        const int jc = t + T * jj;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int64_t off = (int64_t)(n1 * N2 + jc) * sN;
+#pragma unroll
+            for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = ld<S>(ps[s] + off);
+        }
+    }
+
+    double gm_acc = 0.0;  // marginal accumulator of this thread
+    double gb_acc = 0.0;  // dL/dB accumulator of this thread
+    if constexpr (NST == 2) {
+        if (a.gflags & G_MIN) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
+        }
+    }
+
+    if (a.vmode == 1) {
+#pragma unroll
+        for (int jj = 0; jj < JA; ++jj) {
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) {
+                int c[4];
+                elem_coord<AXIS>(i1, j1, i2, j2, n1 * N2 + t + T * jj, c);
+                const double2 f = vfactor(a, c[0], c[1], c[2], c[3]);
+#pragma unroll
+                for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = cmul(v[s][jj * N1 + n1], f);
+            }
+        }
+    }
+
+    // ---- forward transform, stage A: DFT_n1 over n1 for each of the thread's columns
+#pragma unroll
+    for (int s = 0; s < NST; ++s) {
+#pragma unroll
+        for (int jj = 0; jj < JA; ++jj) {
+            dft<N1, -1>(&v[s][jj * N1]);
+            if constexpr (N2 > 1) {
+                const int jc = t + T * jj;
+#pragma unroll
+                for (int k1 = 1; k1 < N1; ++k1) v[s][jj * N1 + k1] = cmul(v[s][jj * N1 + k1], a.tw[(jc * k1) % N]);
+            }
+        }
+    }
+
+    const int LS = W + 1;  // padded LDS row (complex elements) for one position across W lines
+    if constexpr (N2 > 1) {
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+                for (int k1 = 0; k1 < N1; ++k1)
+                    lds[(s * N + k1 * N2 + t + T * jj) * LS + cl] = v[s][jj * N1 + k1];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int ii = 0; ii < IB; ++ii)
+#pragma unroll
+                for (int j = 0; j < N2; ++j) v[s][ii * N2 + j] = lds[(s * N + (t + T * ii) * N2 + j) * LS + cl];
+        // stage B: DFT_n2 over the columns; element (ii, k2) is wave number k1 + n1 * k2
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int ii = 0; ii < IB; ++ii) dft<N2, -1>(&v[s][ii * N2]);
+    }
+
+    // ---- reciprocal space: gradient contribution and the kinetic phase
+    const int yrow = (AXIS == AX_X1) ? j1 : ((AXIS == AX_X2) ? j2 : 0);
+    const double2* kt = a.ktab + ((AXIS == AX_X1 || AX_X2 == AXIS) ? (int64_t)yrow * N : 0);
+    if constexpr (NST == 2 && (AXIS == AX_X1 || AXIS == AX_X2)) {
+        if (a.gflags & G_GB) {
+            const double yv = a.y0 + a.ystep * yrow;
+            const double shift = yv * a.b_eoh;
+#pragma unroll
+            for (int ii = 0; ii < IB; ++ii)
+#pragma unroll
+                for (int k2 = 0; k2 < N2; ++k2) {
+                    const int k = t + T * ii + N1 * k2;
+                    const int m = (k < (N + 1) / 2) ? k : k - N;
+                    const double dth = a.db_coef * (a.kstep * m - shift) * yv;
+                    gb_acc += dth * im_cl_p(v[1][ii * N2 + k2], v[0][ii * N2 + k2]);
+                }
+        }
+    }
+#pragma unroll
+    for (int ii = 0; ii < IB; ++ii)
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+            const int k = t + T * ii + N1 * k2;
+            double2 f = kt[k];
+            if (a.kconj) f = conjd(f);
+#pragma unroll
+            for (int s = 0; s < NST; ++s) v[s][ii * N2 + k2] = cmul(v[s][ii * N2 + k2], f);
+        }
+
+    // ---- inverse transform: the forward network transposed
+    if constexpr (N2 > 1) {
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int ii = 0; ii < IB; ++ii) dft<N2, 1>(&v[s][ii * N2]);
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int ii = 0; ii < IB; ++ii)
+#pragma unroll
+                for (int j = 0; j < N2; ++j) lds[(s * N + (t + T * ii) * N2 + j) * LS + cl] = v[s][ii * N2 + j];
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+                for (int k1 = 0; k1 < N1; ++k1)
+                    v[s][jj * N1 + k1] = lds[(s * N + k1 * N2 + t + T * jj) * LS + cl];
+    }
+#pragma unroll
+    for (int s = 0; s < NST; ++s) {
+#pragma unroll
+        for (int jj = 0; jj < JA; ++jj) {
+            if constexpr (N2 > 1) {
+                const int jc = t + T * jj;
+#pragma unroll
+                for (int k1 = 1; k1 < N1; ++k1) v[s][jj * N1 + k1] = cmulc(v[s][jj * N1 + k1], a.tw[(jc * k1) % N]);
+            }
+            dft<N1, 1>(&v[s][jj * N1]);
+        }
+    }
+
+    if (a.vmode == 2) {
+#pragma unroll
+        for (int jj = 0; jj < JA; ++jj) {
+#pragma unroll
+            for (int n1 = 0; n1 < N1; ++n1) {
+                int c[4];
+                elem_coord<AXIS>(i1, j1, i2, j2, n1 * N2 + t + T * jj, c);
+                const double2 f = vfactor(a, c[0], c[1], c[2], c[3]);
+#pragma unroll
+                for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = cmul(v[s][jj * N1 + n1], f);
+            }
+        }
+    }
+
+    if constexpr (NST == 2) {
+        if (a.gflags & G_MOUT) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
+        }
+    }
+
+#pragma unroll
+    for (int jj = 0; jj < JA; ++jj) {
+        const int jc = t + T * jj;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const int64_t off = (int64_t)(n1 * N2 + jc) * sN;
+#pragma unroll
+            for (int s = 0; s < NST; ++s) st<S>(ps[s] + off, v[s][jj * N1 + n1]);
+        }
+    }
+
+    if constexpr (NST == 2) {
+        double* red = reinterpret_cast<double*>(lds);
+        if (a.gflags & G_GB) {
+            const double s = block_sum(gb_acc, red);
+            if (tid == 0) a.gb_part[blockIdx.x] += s;
+        }
+        if (a.gflags & (G_MIN | G_MOUT)) {
+            if constexpr (AXIS == AX_X1 || AXIS == AX_Y1) {
+                // one marginal slot per line: sum the t threads of the line in fixed order
+                __syncthreads();
+                red[t * W + cl] = gm_acc;
+                __syncthreads();
+                if (t == 0) {
+                    double s = 0.0;
+                    for (int q = 0; q < T; ++q) s += red[q * W + cl];
+                    a.marg_part[line] += s;
+                }
+            } else {
+                // the block's lines share r1: one slot per block
+                const double s = block_sum(gm_acc, red);
+                if (tid == 0) a.marg_part[blockIdx.x] += s;
+            }
+        }
+    }
+}
+
+using AxisKernel = void (*)(const PassArgs);
+
+template <class S, int AXIS, int NST>
+AxisKernel pick(int n, int* t) {
+    switch (n) {
+        case 4: *t = 1; return k_axis<S, AXIS, 4, 1, 1, NST>;
+        case 6: *t = 1; return k_axis<S, AXIS, 6, 1, 1, NST>;
+        case 8: *t = 1; return k_axis<S, AXIS, 8, 1, 1, NST>;
+        case 12: *t = 1; return k_axis<S, AXIS, 12, 1, 1, NST>;
+        case 16: *t = 4; return k_axis<S, AXIS, 4, 4, 4, NST>;
+        case 24: *t = 2; return k_axis<S, AXIS, 12, 2, 2, NST>;
+        case 32: *t = 4; return k_axis<S, AXIS, 8, 4, 4, NST>;
+        case 48: *t = 4; return k_axis<S, AXIS, 12, 4, 4, NST>;
+        case 64: *t = 8; return k_axis<S, AXIS, 8, 8, 8, NST>;
+        case 96: *t = 4; return k_axis<S, AXIS, 12, 8, 4, NST>;
+        case 128: *t = 8; return k_axis<S, AXIS, 16, 8, 8, NST>;
+        case 256: *t = 16; return k_axis<S, AXIS, 16, 16, 16, NST>;
+        default: *t = 0; return nullptr;
+    }
+}
+
+template <class S, int NST>
+AxisKernel pick_axis(int axis, int n, int* t) {
+    switch (axis) {
+        case AX_X1: return pick<S, AX_X1, NST>(n, t);
+        case AX_Y1: return pick<S, AX_Y1, NST>(n, t);
+        case AX_X2: return pick<S, AX_X2, NST>(n, t);
+        case AX_Y2: return pick<S, AX_Y2, NST>(n, t);
+        default: *t = 0; return nullptr;
+    }
+}
+
+}  // namespace dev
+}  // namespace hom4d_impl

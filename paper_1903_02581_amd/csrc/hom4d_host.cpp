@@ -1,0 +1,844 @@
+// Host side of the C ABI declared in include/hom4d.h: argument validation,
+// FP64 phase/twiddle tables, the step driver, observables, entanglement and
+// the reverse (adjoint) sweep.
+//
+// Method: arXiv 1903.02581, Sec. II.C Eq. (evoloperat) and Appendix A (split-
+// step Fourier propagation of two electrons), Eq. (coulomb) and
+// Eq. (screenedCoulomb) (two-body term), Eq. (p_bunching) (region
+// probabilities), Eq. (reduced_density) (spatial entanglement).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hom4d.h"
+#include "hom4d_internal.hpp"
+
+using namespace hom4d_impl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(HOM4D_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                \
+    } while (0)
+
+// CODATA 2018 SI values.
+constexpr double kHbarSI = 1.054571817e-34;   // J s
+constexpr double kQeSI = 1.602176634e-19;     // C
+constexpr double kMeSI = 9.1093837015e-31;    // kg
+constexpr double kEps0SI = 8.8541878128e-12;  // F/m
+constexpr long double kPiL = 3.141592653589793238462643383279502884L;
+
+struct Units {
+    double hbar;    // meV fs
+    double kappa;   // hbar^2 / 2m*, meV nm^2
+    double kc;      // e^2 / 4 pi eps0 eps_r, meV nm
+    double eoh;     // e / hbar, 1/(T nm^2)
+};
+
+Units units_for(const hom4d_cfg& c) {
+    Units u;
+    u.hbar = kHbarSI / kQeSI * 1e3 * 1e15;
+    u.kappa = kHbarSI * kHbarSI / (2.0 * c.mstar_rel * kMeSI) / kQeSI * 1e3 * 1e18;
+    u.kc = kQeSI * kQeSI / (4.0 * (double)kPiL * kEps0SI * c.eps_r) / kQeSI * 1e3 * 1e9;
+    u.eoh = kQeSI / kHbarSI * 1e-18;
+    return u;
+}
+
+// theta - 2 pi rint(theta / 2 pi) with a three-part 2 pi (Cody & Waite).
+double reduce_2pi(double th) {
+    const double c1 = 6.28125, c2 = 0.001935307179586477, c3 = -1.0033115225336665e-19;
+    const double q = std::rint(th * 0.15915494309189535);
+    return std::fma(-q, c3, std::fma(-q, c2, std::fma(-q, c1, th)));
+}
+
+// exp(-i theta) * scale, angle reduced first
+void phase(double th, double scale, double* out) {
+    const double r = reduce_2pi(th);
+    out[0] = std::cos(r) * scale;
+    out[1] = -std::sin(r) * scale;
+}
+
+bool supported_n(int n) {
+    FftShape s;
+    return fft_shape(n, &s);
+}
+
+int validate(const hom4d_cfg* c) {
+    if (!c) return fail(HOM4D_EINVAL, "cfg is NULL");
+    if (!supported_n(c->nx) || !supported_n(c->ny))
+        return fail(HOM4D_EINVAL, "nx=%d ny=%d: each must be one of 4 6 8 12 16 24 32 48 64 96 128 256", c->nx,
+                    c->ny);
+    if (c->precision != HOM4D_FP64 && c->precision != HOM4D_MIXED)
+        return fail(HOM4D_EINVAL, "precision=%d: use HOM4D_FP64 or HOM4D_MIXED", c->precision);
+    if (c->coulomb_mode != HOM4D_COULOMB_TABLE && c->coulomb_mode != HOM4D_COULOMB_DIRECT)
+        return fail(HOM4D_EINVAL, "coulomb_mode=%d", c->coulomb_mode);
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(c->lx_nm) || !pos(c->ly_nm)) return fail(HOM4D_EINVAL, "box lengths must be positive");
+    if (!pos(c->mstar_rel) || !pos(c->eps_r)) return fail(HOM4D_EINVAL, "m* and eps_r must be positive");
+    if (!pos(c->dt_fs)) return fail(HOM4D_EINVAL, "dt must be positive");
+    if (!std::isfinite(c->b_tesla)) return fail(HOM4D_EINVAL, "B must be finite");
+    if (!std::isfinite(c->coulomb_c)) return fail(HOM4D_EINVAL, "coulomb_c must be finite");
+    if (c->coulomb_c != 0.0 && !pos(c->soft_nm))
+        return fail(HOM4D_EINVAL, "soft_nm must be positive when the Coulomb term is on");
+    if (!(std::isfinite(c->screen_nm) && c->screen_nm >= 0.0)) return fail(HOM4D_EINVAL, "screen_nm must be >= 0");
+    const double pts = (double)c->nx * c->ny * (double)c->nx * c->ny;
+    if (pts > 4.3e9) return fail(HOM4D_EINVAL, "state too large");
+    return HOM4D_OK;
+}
+
+struct AxisPlan {
+    int n, t, W;
+    int64_t nlines;
+    size_t lds;
+};
+
+int64_t ilog2_pow2_divisor(int64_t v) {  // largest power of two dividing v
+    return v & (-v);
+}
+
+AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad) {
+    AxisPlan p{};
+    p.n = (axis == AX_X1 || axis == AX_X2) ? nx : ny;
+    FftShape sh;
+    fft_shape(p.n, &sh);
+    p.t = sh.t;
+    const int64_t nxy = (int64_t)nx * ny;
+    p.nlines = nxy * nxy / p.n;
+    int64_t w = 256 / sh.t;
+    if (sh.n2 > 1) {
+        const int64_t cap = 65536 / ((int64_t)nst * p.n * 16) - 1;
+        while (w > cap) w >>= 1;
+    }
+    w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
+    if (axis == AX_X2) w = std::min<int64_t>(w, ilog2_pow2_divisor(ny));
+    if (axis == AX_Y2 && grad) w = std::min<int64_t>(w, ilog2_pow2_divisor(nx));
+    if (w < 1) w = 1;
+    p.W = (int)w;
+    size_t ex = sh.n2 > 1 ? (size_t)nst * p.n * (p.W + 1) * sizeof(double2) : 0;
+    size_t red = nst == 2 ? (size_t)sh.t * p.W * sizeof(double) : 0;
+    p.lds = std::max(ex, red);
+    return p;
+}
+
+bool env_sync_check() {
+    const char* e = std::getenv("HOM4D_SYNC_CHECK");
+    return e && e[0] == '1';
+}
+
+}  // namespace
+
+struct hom4d {
+    hom4d_cfg cfg;
+    Units u;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool mixed = false;
+    bool sync_check = false;
+    int nxy = 0;
+    int64_t npts = 0;
+    size_t state_bytes = 0;
+    // device tables (FP64)
+    double2* tw_x = nullptr;     // [nx]
+    double2* tw_y = nullptr;     // [ny]
+    double2* kx_half = nullptr;  // [ny][nx]  exp(-i theta_x(dt/2)) / nx
+    double2* kx_full = nullptr;  // [ny][nx]  exp(-i theta_x(dt)) / nx
+    double2* ky_full = nullptr;  // [ny]      exp(-i theta_y(dt)) / ny
+    double2* a1_half = nullptr;  // [nx*ny]   exp(-i (dt/2) V / hbar)
+    double2* ac_half = nullptr;  // [(2nx-1)(2ny-1)]
+    double* v_dev = nullptr;     // [nx*ny] meV
+    double* w_dev = nullptr;     // [nx*ny] region weights
+    double* red_part = nullptr;  // reduction partials
+    double* red_out = nullptr;   // 8 doubles
+    double* host_out = nullptr;  // pinned, 8 doubles
+    int red_blocks = 0;
+    // slices
+    int32_t* ix_dev = nullptr;   // 512 ints
+    double2* slice_dev = nullptr;// 256*256
+    double2* orb_dev = nullptr;  // 2 * nx*ny
+    // state
+    void* psi = nullptr;
+    int64_t step = 0;
+    bool have_v = false;
+    double norm_tol = 1e-6;
+    // gradient recording
+    bool rec = false;
+    int ckpt_every = 0;
+    char* pool = nullptr;
+    size_t pool_bytes = 0;
+    int64_t rec_steps = 0;
+    double* g_buf = nullptr;     // all gradient partials
+    size_t g_len = 0;
+};
+
+namespace {
+
+int upload(hom4d* h, void* dst, const void* src, size_t bytes) {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return HOM4D_OK;
+}
+
+double xgrid(const hom4d_cfg& c, int i) { return -0.5 * c.lx_nm + i * (c.lx_nm / c.nx); }
+double ygrid(const hom4d_cfg& c, int j) { return -0.5 * c.ly_nm + j * (c.ly_nm / c.ny); }
+// angular wave number of FFT index m for n points over length L (Nyquist -> negative)
+double kgrid(int n, double len, int m) {
+    const int mm = (m < (n + 1) / 2) ? m : m - n;
+    return 2.0 * M_PI * (mm * (1.0 / (n * (len / n))));
+}
+
+int build_twiddles(hom4d* h) {
+    for (int axis = 0; axis < 2; ++axis) {
+        const int n = axis == 0 ? h->cfg.nx : h->cfg.ny;
+        std::vector<double2> tw(n);
+        for (int j = 0; j < n; ++j) {
+            const long double a = 2.0L * kPiL * (long double)j / (long double)n;
+            tw[j] = make_double2((double)cosl(a), (double)-sinl(a));
+        }
+        int rc = upload(h, axis == 0 ? h->tw_x : h->tw_y, tw.data(), n * sizeof(double2));
+        if (rc) return rc;
+    }
+    return HOM4D_OK;
+}
+
+int build_kinetic(hom4d* h) {
+    const hom4d_cfg& c = h->cfg;
+    const double eb = h->u.eoh * c.b_tesla;
+    for (int which = 0; which < 2; ++which) {
+        const double tau = which == 0 ? 0.5 * c.dt_fs : c.dt_fs;
+        std::vector<double2> t((size_t)c.ny * c.nx);
+        for (int j = 0; j < c.ny; ++j) {
+            const double shift = ygrid(c, j) * eb;
+            for (int m = 0; m < c.nx; ++m) {
+                const double q = kgrid(c.nx, c.lx_nm, m) - shift;
+                const double th = (tau / h->u.hbar) * h->u.kappa * (q * q);
+                double f[2];
+                phase(th, 1.0 / c.nx, f);
+                t[(size_t)j * c.nx + m] = make_double2(f[0], f[1]);
+            }
+        }
+        int rc = upload(h, which == 0 ? h->kx_half : h->kx_full, t.data(), t.size() * sizeof(double2));
+        if (rc) return rc;
+    }
+    std::vector<double2> ty(c.ny);
+    for (int m = 0; m < c.ny; ++m) {
+        const double k = kgrid(c.ny, c.ly_nm, m);
+        const double th = (c.dt_fs / h->u.hbar) * h->u.kappa * (k * k);
+        double f[2];
+        phase(th, 1.0 / c.ny, f);
+        ty[m] = make_double2(f[0], f[1]);
+    }
+    return upload(h, h->ky_full, ty.data(), ty.size() * sizeof(double2));
+}
+
+int build_coulomb(hom4d* h) {
+    const hom4d_cfg& c = h->cfg;
+    const int ax = 2 * c.nx - 1, ay = 2 * c.ny - 1;
+    std::vector<double2> t((size_t)ax * ay);
+    const double dx = c.lx_nm / c.nx, dy = c.ly_nm / c.ny;
+    const double tau = 0.5 * c.dt_fs;
+    for (int di = 0; di < ax; ++di)
+        for (int dj = 0; dj < ay; ++dj) {
+            const double ddx = (di - (c.nx - 1)) * dx, ddy = (dj - (c.ny - 1)) * dy;
+            const double r2 = ddx * ddx + ddy * ddy;
+            double v = c.coulomb_c * h->u.kc / std::sqrt(r2 + c.soft_nm * c.soft_nm);
+            if (c.screen_nm > 0.0) v *= std::exp(-std::sqrt(r2) / c.screen_nm);
+            double f[2];
+            phase((tau / h->u.hbar) * v, 1.0, f);
+            t[(size_t)di * ay + dj] = make_double2(f[0], f[1]);
+        }
+    return upload(h, h->ac_half, t.data(), t.size() * sizeof(double2));
+}
+
+int sync_check(hom4d* h, const char* what) {
+    if (!h->sync_check) return HOM4D_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(HOM4D_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return HOM4D_OK;
+}
+
+enum KTab { KX_HALF, KX_FULL, KY_FULL };
+
+struct GradCtx {
+    double* gb_x1;
+    double* gb_x2;
+    double* m_x1;
+    double* m_y1;
+    double* m_x2;
+    double* m_y2;
+};
+
+int run_pass(hom4d* h, int axis, KTab kt, int vmode, int nst, void* lam, bool reverse, int gflags,
+             const GradCtx* g) {
+    const hom4d_cfg& c = h->cfg;
+    AxisPlan p = plan_axis(axis, c.nx, c.ny, nst, nst == 2);
+    PassArgs a{};
+    a.psi = h->psi;
+    a.lam = lam;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.W = p.W;
+    a.kconj = reverse ? 1 : 0;
+    a.tw = (axis == AX_X1 || axis == AX_X2) ? h->tw_x : h->tw_y;
+    a.ktab = kt == KX_HALF ? h->kx_half : (kt == KX_FULL ? h->kx_full : h->ky_full);
+    a.vmode = vmode;
+    a.a1 = h->a1_half;
+    a.ac = (c.coulomb_c != 0.0) ? h->ac_half : nullptr;
+    a.vdirect = c.coulomb_mode == HOM4D_COULOMB_DIRECT ? 1 : 0;
+    a.vtab = h->v_dev;
+    a.vscale = (reverse ? -0.5 : 0.5) * c.dt_fs / h->u.hbar;
+    a.dx = c.lx_nm / c.nx;
+    a.dy = c.ly_nm / c.ny;
+    a.soft2 = c.soft_nm * c.soft_nm;
+    a.ck = c.coulomb_c * h->u.kc;
+    a.inv_screen = c.screen_nm > 0.0 ? 1.0 / c.screen_nm : 0.0;
+    a.gflags = gflags;
+    if (nst == 2 && g) {
+        const double tau = kt == KX_FULL ? c.dt_fs : 0.5 * c.dt_fs;
+        a.db_coef = (tau / h->u.hbar) * h->u.kappa * 2.0 * (-h->u.eoh);
+        a.b_eoh = h->u.eoh * c.b_tesla;
+        a.kstep = 2.0 * M_PI / c.lx_nm;
+        a.y0 = -0.5 * c.ly_nm;
+        a.ystep = c.ly_nm / c.ny;
+        if (axis == AX_X1) { a.gb_part = g->gb_x1; a.marg_part = g->m_x1; }
+        if (axis == AX_X2) { a.gb_part = g->gb_x2; a.marg_part = g->m_x2; }
+        if (axis == AX_Y1) { a.marg_part = g->m_y1; }
+        if (axis == AX_Y2) { a.marg_part = g->m_y2; }
+    }
+    if (vmode && !h->have_v) return fail(HOM4D_ESTATE, "no potential set (hom4d_set_potential)");
+    HIP_TRY(launch_axis(axis, p.n, h->mixed, nst, a, p.nlines, p.lds, h->stream));
+    return sync_check(h, "axis pass");
+}
+
+// n whole steps with merged X halves; the state is closed at the end.
+int run_steps(hom4d* h, int64_t n, int nst, void* lam, bool reverse, const GradCtx* g) {
+    if (n <= 0) return HOM4D_OK;
+    const bool gr = nst == 2;
+    int rc;
+    if ((rc = run_pass(h, AX_X1, KX_HALF, 0, nst, lam, reverse, gr ? G_GB : 0, g))) return rc;
+    if ((rc = run_pass(h, AX_X2, KX_HALF, 0, nst, lam, reverse, gr ? (G_GB | G_MOUT) : 0, g))) return rc;
+    for (int64_t i = 0; i < n; ++i) {
+        const bool last = i == n - 1;
+        if ((rc = run_pass(h, AX_Y1, KY_FULL, 1, nst, lam, reverse, gr ? G_MIN : 0, g))) return rc;
+        if ((rc = run_pass(h, AX_Y2, KY_FULL, 2, nst, lam, reverse, gr ? G_MOUT : 0, g))) return rc;
+        const KTab kx = last ? KX_HALF : KX_FULL;
+        if ((rc = run_pass(h, AX_X1, kx, 0, nst, lam, reverse, gr ? (G_GB | G_MIN) : 0, g))) return rc;
+        if ((rc = run_pass(h, AX_X2, kx, 0, nst, lam, reverse, gr ? (G_GB | (last ? 0 : G_MOUT)) : 0, g)))
+            return rc;
+    }
+    return HOM4D_OK;
+}
+
+int fetch_reduction(hom4d* h, int width, double* out) {
+    HIP_TRY(launch_reduce_parts(h->red_part, h->red_blocks, width, h->red_out, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->host_out, h->red_out, width * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int q = 0; q < width; ++q) out[q] = h->host_out[q];
+    return HOM4D_OK;
+}
+
+int check_weights(const double* w, int n) {
+    if (!w) return fail(HOM4D_EINVAL, "w_top is NULL");
+    for (int i = 0; i < n; ++i)
+        if (!(w[i] >= 0.0 && w[i] <= 1.0)) return fail(HOM4D_EINVAL, "w_top[%d] = %g outside [0, 1]", i, w[i]);
+    return HOM4D_OK;
+}
+
+// Eigenvalues of a real symmetric matrix (row-major, n x n, destroyed), cyclic Jacobi.
+void jacobi_eigenvalues(std::vector<double>& a, int n, std::vector<double>& ev) {
+    auto A = [&](int i, int j) -> double& { return a[(size_t)i * n + j]; };
+    double diag2 = 0.0;
+    for (int i = 0; i < n; ++i) diag2 += A(i, i) * A(i, i);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += A(p, q) * A(p, q);
+        if (off <= 1e-32 * std::max(diag2, 1e-300)) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A(p, q);
+                if (std::fabs(apq) < 1e-300) continue;
+                const double zeta = (A(q, q) - A(p, p)) / (2.0 * apq);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(zeta * zeta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = A(k, p), akq = A(k, q);
+                    A(k, p) = c * akp - s * akq;
+                    A(k, q) = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A(p, k), aqk = A(q, k);
+                    A(p, k) = c * apk - s * aqk;
+                    A(q, k) = s * apk + c * aqk;
+                }
+            }
+    }
+    ev.resize(n);
+    for (int i = 0; i < n; ++i) ev[i] = A(i, i);
+}
+
+int slice_checks(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1, const int32_t* ix2, int32_t n2,
+                 int32_t jy2) {
+    const hom4d_cfg& c = h->cfg;
+    if (!ix1 || !ix2) return fail(HOM4D_EINVAL, "index array is NULL");
+    if (n1 < 1 || n1 > 256 || n2 < 1 || n2 > 256) return fail(HOM4D_EINVAL, "slice sizes must be in [1, 256]");
+    if (jy1 < 0 || jy1 >= c.ny || jy2 < 0 || jy2 >= c.ny) return fail(HOM4D_EINVAL, "y slice index out of range");
+    for (int i = 0; i < n1; ++i)
+        if (ix1[i] < 0 || ix1[i] >= c.nx) return fail(HOM4D_EINVAL, "ix1[%d] out of range", i);
+    for (int i = 0; i < n2; ++i)
+        if (ix2[i] < 0 || ix2[i] >= c.nx) return fail(HOM4D_EINVAL, "ix2[%d] out of range", i);
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    return HOM4D_OK;
+}
+
+int gather(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1, const int32_t* ix2, int32_t n2, int32_t jy2,
+           std::vector<double>& out) {
+    int rc = slice_checks(h, ix1, n1, jy1, ix2, n2, jy2);
+    if (rc) return rc;
+    std::vector<int32_t> idx(512, 0);
+    std::memcpy(idx.data(), ix1, n1 * sizeof(int32_t));
+    std::memcpy(idx.data() + 256, ix2, n2 * sizeof(int32_t));
+    HIP_TRY(hipMemcpyAsync(h->ix_dev, idx.data(), 512 * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(launch_gather(h->psi, h->mixed, h->ix_dev, n1, jy1, h->ix_dev + 256, n2, jy2, h->cfg.nx, h->cfg.ny,
+                          h->slice_dev, h->stream));
+    out.resize((size_t)2 * n1 * n2);
+    HIP_TRY(hipMemcpyAsync(out.data(), h->slice_dev, (size_t)n1 * n2 * sizeof(double2), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return HOM4D_OK;
+}
+
+void free_all(hom4d* h) {
+    void* bufs[] = {h->tw_x, h->tw_y, h->kx_half, h->kx_full, h->ky_full, h->a1_half, h->ac_half, h->v_dev,
+                    h->w_dev, h->red_part, h->red_out, h->ix_dev, h->slice_dev, h->orb_dev, h->g_buf};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (h->host_out) (void)hipHostFree(h->host_out);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hom4d_validate_cfg(const hom4d_cfg* cfg) { return validate(cfg); }
+
+size_t hom4d_state_bytes(const hom4d_cfg* cfg) {
+    if (validate(cfg) != HOM4D_OK) return 0;
+    const size_t nxy = (size_t)cfg->nx * cfg->ny;
+    return nxy * nxy * (cfg->precision == HOM4D_MIXED ? 8 : 16);
+}
+
+int hom4d_create(const hom4d_cfg* cfg, void* hip_stream, hom4d** out) {
+    if (!out) return fail(HOM4D_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    hom4d* h = new hom4d();
+    h->cfg = *cfg;
+    h->u = units_for(*cfg);
+    h->stream = (hipStream_t)hip_stream;
+    h->mixed = cfg->precision == HOM4D_MIXED;
+    h->sync_check = env_sync_check();
+    h->nxy = cfg->nx * cfg->ny;
+    h->npts = (int64_t)h->nxy * h->nxy;
+    h->state_bytes = hom4d_state_bytes(cfg);
+    h->red_blocks = std::min(h->nxy, 1024);
+    auto cleanup = [&](int code) {
+        free_all(h);
+        delete h;
+        return code;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        fail(HOM4D_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+        return cleanup(HOM4D_EHIP);
+    }
+    const int nx = cfg->nx, ny = cfg->ny;
+    struct {
+        void** p;
+        size_t bytes;
+    } allocs[] = {
+        {(void**)&h->tw_x, nx * sizeof(double2)},
+        {(void**)&h->tw_y, ny * sizeof(double2)},
+        {(void**)&h->kx_half, (size_t)nx * ny * sizeof(double2)},
+        {(void**)&h->kx_full, (size_t)nx * ny * sizeof(double2)},
+        {(void**)&h->ky_full, ny * sizeof(double2)},
+        {(void**)&h->a1_half, (size_t)nx * ny * sizeof(double2)},
+        {(void**)&h->ac_half, (size_t)(2 * nx - 1) * (2 * ny - 1) * sizeof(double2)},
+        {(void**)&h->v_dev, (size_t)nx * ny * sizeof(double)},
+        {(void**)&h->w_dev, (size_t)nx * ny * sizeof(double)},
+        {(void**)&h->red_part, (size_t)h->red_blocks * 8 * sizeof(double)},
+        {(void**)&h->red_out, 8 * sizeof(double)},
+        {(void**)&h->ix_dev, 512 * sizeof(int32_t)},
+        {(void**)&h->slice_dev, 256 * 256 * sizeof(double2)},
+        {(void**)&h->orb_dev, (size_t)2 * nx * ny * sizeof(double2)},
+    };
+    for (auto& a : allocs) {
+        e = hipMalloc(a.p, a.bytes);
+        if (e != hipSuccess) {
+            fail(HOM4D_EHIP, "hipMalloc(%zu): %s", a.bytes, hipGetErrorString(e));
+            return cleanup(HOM4D_EHIP);
+        }
+    }
+    e = hipHostMalloc((void**)&h->host_out, 8 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        fail(HOM4D_EHIP, "hipHostMalloc: %s", hipGetErrorString(e));
+        return cleanup(HOM4D_EHIP);
+    }
+    if ((rc = build_twiddles(h)) || (rc = build_kinetic(h)) || (rc = build_coulomb(h))) return cleanup(rc);
+    *out = h;
+    return HOM4D_OK;
+}
+
+int hom4d_destroy(hom4d* h) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+    return HOM4D_OK;
+}
+
+int hom4d_bind_state(hom4d* h, void* d_psi) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!d_psi) return fail(HOM4D_EINVAL, "state pointer is NULL");
+    if (((uintptr_t)d_psi) % 16 != 0) return fail(HOM4D_EINVAL, "state pointer must be 16-byte aligned");
+    h->psi = d_psi;
+    h->rec = false;
+    return HOM4D_OK;
+}
+
+int hom4d_set_potential(hom4d* h, const double* v) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!v) return fail(HOM4D_EINVAL, "potential is NULL");
+    const hom4d_cfg& c = h->cfg;
+    std::vector<double2> a1((size_t)c.nx * c.ny);
+    for (int i = 0; i < c.nx * c.ny; ++i) {
+        if (!std::isfinite(v[i])) return fail(HOM4D_EINVAL, "V[%d] is not finite", i);
+        double f[2];
+        phase((0.5 * c.dt_fs / h->u.hbar) * v[i], 1.0, f);
+        a1[i] = make_double2(f[0], f[1]);
+    }
+    int rc = upload(h, h->a1_half, a1.data(), a1.size() * sizeof(double2));
+    if (rc) return rc;
+    rc = upload(h, h->v_dev, v, (size_t)c.nx * c.ny * sizeof(double));
+    if (rc) return rc;
+    h->have_v = true;
+    return HOM4D_OK;
+}
+
+int hom4d_set_field(hom4d* h, double b) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!std::isfinite(b)) return fail(HOM4D_EINVAL, "B must be finite");
+    h->cfg.b_tesla = b;
+    return build_kinetic(h);
+}
+
+int hom4d_set_norm_tol(hom4d* h, double tol) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!(tol > 0.0)) return fail(HOM4D_EINVAL, "tolerance must be positive");
+    h->norm_tol = tol;
+    return HOM4D_OK;
+}
+
+int hom4d_init_state(hom4d* h, const double* psi_a, const double* psi_b, int32_t sym) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!psi_a || !psi_b) return fail(HOM4D_EINVAL, "orbital is NULL");
+    if (sym != -1 && sym != 0 && sym != 1) return fail(HOM4D_EINVAL, "sym=%d: use -1, 0 or +1", sym);
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    const size_t nb = (size_t)h->nxy * sizeof(double2);
+    HIP_TRY(hipMemcpyAsync(h->orb_dev, psi_a, nb, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->orb_dev + h->nxy, psi_b, nb, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(launch_init_norm(h->orb_dev, h->orb_dev + h->nxy, sym, h->nxy, h->red_part, h->red_blocks, h->stream));
+    double nrm = 0.0;
+    int rc = fetch_reduction(h, 1, &nrm);
+    if (rc) return rc;
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return fail(HOM4D_EINVAL, "initial state has norm %g", nrm);
+    HIP_TRY(launch_init_write(h->psi, h->mixed, h->orb_dev, h->orb_dev + h->nxy, sym, h->nxy, 1.0 / std::sqrt(nrm),
+                              h->stream));
+    h->step = 0;
+    h->rec = false;
+    return sync_check(h, "init");
+}
+
+int hom4d_load_state(hom4d* h, const double* psi4d) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!psi4d) return fail(HOM4D_EINVAL, "state is NULL");
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    if (!h->mixed) {
+        HIP_TRY(hipMemcpyAsync(h->psi, psi4d, h->state_bytes, hipMemcpyHostToDevice, h->stream));
+    } else {
+        // round to complex64 on the host in chunks
+        const int64_t chunk = 1 << 22;
+        std::vector<float> buf((size_t)2 * chunk);
+        for (int64_t o = 0; o < h->npts; o += chunk) {
+            const int64_t m = std::min(chunk, h->npts - o);
+            for (int64_t i = 0; i < 2 * m; ++i) buf[i] = (float)psi4d[2 * o + i];
+            HIP_TRY(hipMemcpyAsync((float2*)h->psi + o, buf.data(), m * sizeof(float2), hipMemcpyHostToDevice,
+                                   h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->step = 0;
+    h->rec = false;
+    return HOM4D_OK;
+}
+
+int hom4d_store_state(hom4d* h, double* psi4d) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!psi4d) return fail(HOM4D_EINVAL, "output is NULL");
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    if (!h->mixed) {
+        HIP_TRY(hipMemcpyAsync(psi4d, h->psi, h->state_bytes, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    } else {
+        const int64_t chunk = 1 << 22;
+        std::vector<float> buf((size_t)2 * chunk);
+        for (int64_t o = 0; o < h->npts; o += chunk) {
+            const int64_t m = std::min(chunk, h->npts - o);
+            HIP_TRY(hipMemcpyAsync(buf.data(), (float2*)h->psi + o, m * sizeof(float2), hipMemcpyDeviceToHost,
+                                   h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            for (int64_t i = 0; i < 2 * m; ++i) psi4d[2 * o + i] = (double)buf[i];
+        }
+    }
+    return HOM4D_OK;
+}
+
+int hom4d_step(hom4d* h, int64_t n) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (n < 0) return fail(HOM4D_EINVAL, "n=%lld must be >= 0", (long long)n);
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    if (!h->have_v) return fail(HOM4D_ESTATE, "no potential set (hom4d_set_potential)");
+    if (!h->rec) {
+        int rc = run_steps(h, n, 1, nullptr, false, nullptr);
+        if (rc) return rc;
+        h->step += n;
+        return HOM4D_OK;
+    }
+    // recording: close the state on every checkpoint boundary and copy it out
+    int64_t left = n;
+    while (left > 0) {
+        const int64_t to_ck = h->ckpt_every - (h->rec_steps % h->ckpt_every);
+        const int64_t m = std::min(left, to_ck);
+        int rc = run_steps(h, m, 1, nullptr, false, nullptr);
+        if (rc) return rc;
+        h->rec_steps += m;
+        h->step += m;
+        left -= m;
+        if (h->rec_steps % h->ckpt_every == 0) {
+            const size_t slot = (size_t)(h->rec_steps / h->ckpt_every);
+            if ((slot + 1) * h->state_bytes > h->pool_bytes)
+                return fail(HOM4D_ENOMEM, "checkpoint %zu does not fit the pool (%zu bytes)", slot, h->pool_bytes);
+            HIP_TRY(hipMemcpyAsync(h->pool + slot * h->state_bytes, h->psi, h->state_bytes, hipMemcpyDeviceToDevice,
+                                   h->stream));
+        }
+    }
+    return HOM4D_OK;
+}
+
+int hom4d_observables(hom4d* h, const double* w_top, hom4d_obs* out) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!out) return fail(HOM4D_EINVAL, "out is NULL");
+    int rc = check_weights(w_top, h->nxy);
+    if (rc) return rc;
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    HIP_TRY(hipMemcpyAsync(h->w_dev, w_top, h->nxy * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(launch_obs(h->psi, h->mixed, h->w_dev, h->nxy, h->red_part, h->red_blocks, h->stream));
+    double r[5];
+    if ((rc = fetch_reduction(h, 5, r))) return rc;
+    out->norm = r[0];
+    out->p_tt = r[1];
+    out->p_tb = r[2];
+    out->p_bt = r[3];
+    out->p_bb = r[4];
+    out->p_b = r[1] + r[4];
+    out->p_ab = r[2] + r[3];
+    out->step = h->step;
+    if (!std::isfinite(r[0])) return fail(HOM4D_ENONFINITE, "state holds non-finite values");
+    if (std::fabs(r[0] - 1.0) > h->norm_tol)
+        return fail(HOM4D_ENORMDRIFT, "norm %.17g drifted beyond %g", r[0], h->norm_tol);
+    return HOM4D_OK;
+}
+
+int hom4d_gather_slice(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1, const int32_t* ix2, int32_t n2,
+                       int32_t jy2, double* out) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!out) return fail(HOM4D_EINVAL, "out is NULL");
+    std::vector<double> phi;
+    int rc = gather(h, ix1, n1, jy1, ix2, n2, jy2, phi);
+    if (rc) return rc;
+    std::memcpy(out, phi.data(), phi.size() * sizeof(double));
+    return HOM4D_OK;
+}
+
+int hom4d_entanglement(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1, const int32_t* ix2, int32_t n2,
+                       int32_t jy2, double* s_out) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!s_out) return fail(HOM4D_EINVAL, "s_out is NULL");
+    std::vector<double> phi;
+    int rc = gather(h, ix1, n1, jy1, ix2, n2, jy2, phi);
+    if (rc) return rc;
+    double nrm = 0.0;
+    for (double x : phi) nrm += x * x;
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return fail(HOM4D_ENONFINITE, "slice norm %g", nrm);
+    // rho over the smaller side: G = phi phi^dagger (n1 <= n2) or phi^dagger phi, Hermitian,
+    // embedded as the real symmetric [[Re, -Im], [Im, Re]] whose spectrum is G's, doubled.
+    const bool left = n1 <= n2;
+    const int m = left ? n1 : n2, kdim = left ? n2 : n1;
+    auto el = [&](int a, int b, double* re, double* im) {  // phi[a][b]
+        *re = phi[2 * ((size_t)a * n2 + b)] / std::sqrt(nrm);
+        *im = phi[2 * ((size_t)a * n2 + b) + 1] / std::sqrt(nrm);
+    };
+    std::vector<double> g((size_t)2 * m * 2 * m, 0.0);
+    for (int p = 0; p < m; ++p)
+        for (int q = 0; q < m; ++q) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < kdim; ++k) {
+                double ar, ai, br, bi;
+                if (left) {
+                    el(p, k, &ar, &ai);
+                    el(q, k, &br, &bi);
+                } else {
+                    el(k, p, &ar, &ai);
+                    el(k, q, &br, &bi);
+                    ai = -ai;
+                    bi = -bi;
+                }
+                re += ar * br + ai * bi;  // a * conj(b)
+                im += ai * br - ar * bi;
+            }
+            const int M = 2 * m;
+            g[(size_t)p * M + q] = re;
+            g[(size_t)(p + m) * M + (q + m)] = re;
+            g[(size_t)p * M + (q + m)] = -im;
+            g[(size_t)(p + m) * M + q] = im;
+        }
+    std::vector<double> ev;
+    jacobi_eigenvalues(g, 2 * m, ev);
+    double s = 0.0;
+    for (double lam : ev)
+        if (lam > 0.0) s -= lam * std::log(lam);
+    *s_out = 0.5 * s;
+    return HOM4D_OK;
+}
+
+int hom4d_grad_begin(hom4d* h, int32_t ckpt_every, void* d_pool, size_t pool_bytes) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (ckpt_every < 1) return fail(HOM4D_EINVAL, "ckpt_every=%d must be >= 1", ckpt_every);
+    if (!d_pool) return fail(HOM4D_EINVAL, "pool is NULL");
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    if (pool_bytes < h->state_bytes) return fail(HOM4D_ENOMEM, "pool smaller than one state");
+    h->ckpt_every = ckpt_every;
+    h->pool = (char*)d_pool;
+    h->pool_bytes = pool_bytes;
+    h->rec_steps = 0;
+    HIP_TRY(hipMemcpyAsync(h->pool, h->psi, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
+    h->rec = true;
+    return HOM4D_OK;
+}
+
+int hom4d_grad_end(hom4d* h) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    h->rec = false;
+    return HOM4D_OK;
+}
+
+int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs, void* d_lambda, double* loss,
+                        double* dL_dV, double* dL_dB) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!coeffs || !d_lambda || !loss || !dL_dV || !dL_dB) return fail(HOM4D_EINVAL, "NULL argument");
+    if (((uintptr_t)d_lambda) % 16 != 0) return fail(HOM4D_EINVAL, "adjoint buffer must be 16-byte aligned");
+    int rc = check_weights(w_top, h->nxy);
+    if (rc) return rc;
+    if (!h->rec) return fail(HOM4D_ESTATE, "no recorded forward run (hom4d_grad_begin + hom4d_step)");
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    const hom4d_cfg& c = h->cfg;
+    const AxisPlan px1 = plan_axis(AX_X1, c.nx, c.ny, 2, true), px2 = plan_axis(AX_X2, c.nx, c.ny, 2, true);
+    const AxisPlan py1 = plan_axis(AX_Y1, c.nx, c.ny, 2, true), py2 = plan_axis(AX_Y2, c.nx, c.ny, 2, true);
+    const int64_t nb_x1 = px1.nlines / px1.W, nb_x2 = px2.nlines / px2.W, nb_y2 = py2.nlines / py2.W;
+    const int64_t len_m_x1 = px1.nlines, len_m_y1 = py1.nlines;
+    const size_t need = (size_t)(nb_x1 + nb_x2 + len_m_x1 + len_m_y1 + nb_x2 + nb_y2 + h->nxy);
+    if (need > h->g_len) {
+        if (h->g_buf) HIP_TRY(hipFree(h->g_buf));
+        h->g_buf = nullptr;
+        HIP_TRY(hipMalloc((void**)&h->g_buf, need * sizeof(double)));
+        h->g_len = need;
+    }
+    GradCtx g;
+    g.gb_x1 = h->g_buf;
+    g.gb_x2 = g.gb_x1 + nb_x1;
+    g.m_x1 = g.gb_x2 + nb_x2;
+    g.m_y1 = g.m_x1 + len_m_x1;
+    g.m_x2 = g.m_y1 + len_m_y1;
+    g.m_y2 = g.m_x2 + nb_x2;
+    double* dldv_dev = g.m_y2 + nb_y2;
+    HIP_TRY(launch_zero(h->g_buf, (int64_t)need, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->w_dev, w_top, h->nxy * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(launch_loss_lambda(h->psi, d_lambda, h->mixed, h->w_dev, coeffs, h->nxy, h->red_part, h->red_blocks,
+                               h->stream));
+    double L = 0.0;
+    if ((rc = fetch_reduction(h, 1, &L))) return rc;
+    // reverse sweep, segment by segment, restoring the state at every checkpoint
+    int64_t seg_end = h->rec_steps;
+    for (int64_t k = h->rec_steps / h->ckpt_every; k >= 0; --k) {
+        const int64_t seg_start = k * h->ckpt_every;
+        if (seg_end > seg_start) {
+            if ((rc = run_steps(h, seg_end - seg_start, 2, d_lambda, true, &g))) return rc;
+        }
+        HIP_TRY(hipMemcpyAsync(h->psi, h->pool + (size_t)k * h->state_bytes, h->state_bytes, hipMemcpyDeviceToDevice,
+                               h->stream));
+        seg_end = seg_start;
+    }
+    HIP_TRY(launch_grad_finish(g.m_x2, (int)(c.ny / px2.W), g.m_y2, (int)(c.nx / py2.W), g.m_y1, g.m_x1, c.nx, c.ny,
+                               c.dt_fs / h->u.hbar, dldv_dev, h->stream));
+    HIP_TRY(hipMemcpyAsync(dL_dV, dldv_dev, h->nxy * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    // dL/dB: both x axes, Parseval factor 1/nx, factor 2 of 2 Im(conj(lambda) psi)
+    HIP_TRY(launch_reduce_parts(g.gb_x1, (int)(nb_x1 + nb_x2), 1, h->red_out, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->host_out, h->red_out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    *dL_dB = h->host_out[0] * 2.0 / c.nx;
+    *loss = L;
+    h->step -= h->rec_steps;
+    h->rec = false;
+    return HOM4D_OK;
+}
+
+const char* hom4d_strerror(int status) {
+    switch (status) {
+        case HOM4D_OK: return "ok";
+        case HOM4D_EINVAL: return "invalid argument";
+        case HOM4D_EUNBOUND: return "no state bound";
+        case HOM4D_ESTATE: return "call out of order";
+        case HOM4D_ENOMEM: return "buffer too small or allocation failed";
+        case HOM4D_EHIP: return "HIP runtime error";
+        case HOM4D_ENONFINITE: return "non-finite state";
+        case HOM4D_ENORMDRIFT: return "norm drift beyond tolerance";
+        default: return "unknown status";
+    }
+}
+
+const char* hom4d_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal interface between the host driver (hom4d_host.cpp) and the device
+// kernels (hom4d_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace hom4d_impl {
+
+enum Axis : int { AX_X1 = 0, AX_Y1 = 1, AX_X2 = 2, AX_Y2 = 3 };
+
+enum GradFlags : int {
+    G_GB = 1,    // accumulate dL/dB contributions in (k_x, y) space (x axes)
+    G_MIN = 2,   // accumulate Im(conj(lambda) psi) marginals of the loaded real-space states
+    G_MOUT = 4,  // ... of the real-space states written back
+};
+
+// Everything one per-axis pass needs.  Axis lines have length n = nx (x axes)
+// or ny (y axes); the 4D state is row-major [x1][y1][x2][y2].
+struct PassArgs {
+    void* psi;                // state, complex128 or complex64
+    void* lam;                // adjoint state (dual-state passes only)
+    int nx, ny;
+    int W;                    // lines per block
+    int kconj;                // use conj(ktab) and conj(potential factor): reverse sweep
+    const double2* tw;        // twiddles exp(-2 pi i j / n), j < n
+    const double2* ktab;      // k-space factor incl. 1/n: [ny][nx] for x axes, [ny] for y axes
+    int vmode;                // 0: none, 1: potential factor before the transform, 2: after
+    // potential factor, table form
+    const double2* a1;        // [nx*ny]  exp(-i tau V(x,y)/hbar)
+    const double2* ac;        // [(2nx-1)*(2ny-1)] exp(-i tau V12(dx,dy)/hbar), or null
+    // potential factor, per-point form (vdirect = 1)
+    int vdirect;
+    const double* vtab;       // [nx*ny] V in meV
+    double vscale;            // tau / hbar (1/meV), signed
+    double dx, dy, soft2, ck, inv_screen;
+    // gradient accumulation (dual-state passes)
+    int gflags;
+    double* gb_part;          // per block
+    double* marg_part;        // per line (x1, y1 axes) or per block (x2, y2 axes)
+    double db_coef;           // (tau/hbar) * kappa * 2 * (-e/hbar)
+    double b_eoh;             // e B / hbar
+    double kstep;             // 2 pi / Lx
+    double y0, ystep;         // y grid
+};
+
+struct FftShape {
+    int n1, n2, t;  // n = n1 * n2, t threads per line
+};
+
+// Supported line lengths and their register/LDS decomposition.
+bool fft_shape(int n, FftShape* out);
+
+// Launch one per-axis pass: blocks of t*W threads, nlines/W blocks.
+hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, int64_t nlines,
+                       size_t lds_bytes, hipStream_t s);
+
+// Reductions and elementwise kernels.
+hipError_t launch_init_norm(const double2* pa, const double2* pb, int sym, int nxy, double* part,
+                            int nblocks, hipStream_t s);
+hipError_t launch_init_write(void* psi, bool mixed, const double2* pa, const double2* pb, int sym,
+                             int nxy, double scale, hipStream_t s);
+hipError_t launch_obs(const void* psi, bool mixed, const double* w, int nxy, double* part, int nblocks,
+                      hipStream_t s);
+hipError_t launch_loss_lambda(const void* psi, void* lam, bool mixed, const double* w,
+                              const double* coeffs_dev, int nxy, double* part, int nblocks,
+                              hipStream_t s);
+hipError_t launch_reduce_parts(const double* part, int nparts, int width, double* out, hipStream_t s);
+hipError_t launch_gather(const void* psi, bool mixed, const int32_t* ix1, int n1, int jy1,
+                         const int32_t* ix2, int n2, int jy2, int nx, int ny, double2* out,
+                         hipStream_t s);
+hipError_t launch_c128_to_c64(const double2* in, float2* out, int64_t count, hipStream_t s);
+hipError_t launch_c64_to_c128(const float2* in, double2* out, int64_t count, hipStream_t s);
+hipError_t launch_grad_finish(const double* m_x2, int bpr_x2, const double* m_y2, int bpr_y2,
+                              const double* m_y1, const double* m_x1, int nx, int ny, double gscale,
+                              double* dldv, hipStream_t s);
+hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
+
+}  // namespace hom4d_impl

@@ -1,0 +1,93 @@
+"""Adjoint gradient of the GPU path against the oracle's stored-state adjoint
+and against central finite differences of the GPU forward run."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads.presets import build
+from tests.gpu_util import announce, grid_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(nx=8, ny=8, steps=6, sym=-1, seed=1):
+    w = build("g", nx, ny, 25.0 * nx, 25.0 * ny, b_tesla=5.0, dt_fs=5.0, steps=steps,
+              sigma_x=20.0, seed=seed, sym=sym)
+    return w
+
+
+@pytest.mark.parametrize("nx,ny,steps,ck,sym", [(8, 8, 6, 2, -1), (16, 8, 7, 3, -1),
+                                                (8, 12, 5, 10, 0), (12, 16, 9, 4, 1)])
+def test_grad_vs_oracle_stored_adjoint(nx, ny, steps, ck, sym):
+    from paper_1903_02581_amd import Propagator
+    w = _case(nx, ny, steps, sym)
+    announce(f"grad fp64 {nx}x{ny} steps={steps} ckpt={ck} sym={sym}")
+    g = grid_of(w)
+    psi0 = O.init_state(w.psi_a, w.psi_b, sym)
+    L, gv, gb = O.loss_and_grad_stored(psi0, g, w.v_table, w.dt_fs, steps, w.w_top)
+    p = Propagator.from_workload(w)
+    p.init_state(w.psi_a, w.psi_b, sym)
+    p.grad_begin(ck, steps)
+    p.step(steps)
+    L2, gv2, gb2 = p.grad_backward(w.w_top)
+    assert abs(L - L2) <= 1e-12
+    assert np.max(np.abs(gv - gv2)) <= 1e-10 * np.max(np.abs(gv))
+    assert abs(gb - gb2) <= 1e-10 * max(abs(gb), 1e-12)
+    assert abs(gv2.sum()) <= 1e-10 * np.abs(gv2).sum()
+    # the state is back at the start of the recording
+    back = p.store_state()
+    assert np.max(np.abs(back - psi0)) <= 1e-13
+    p.close()
+
+
+def test_grad_mixed_close_to_fp64():
+    from paper_1903_02581_amd import Propagator
+    w = _case(16, 16, 20)
+    announce("grad mixed 16x16 steps=20")
+    out = {}
+    for prec in ("fp64", "mixed"):
+        p = Propagator.from_workload(w, precision=prec)
+        p.grad_begin(5, w.steps)
+        p.step(w.steps)
+        out[prec] = p.grad_backward(w.w_top)
+        p.close()
+    (l1, v1, b1), (l2, v2, b2) = out["fp64"], out["mixed"]
+    assert abs(l1 - l2) <= 1e-5
+    assert np.max(np.abs(v1 - v2)) <= 1e-4 * np.max(np.abs(v1))
+    assert abs(b1 - b2) <= 1e-4 * abs(b1)
+
+
+def test_bunching_loss_autograd_vs_finite_differences():
+    import torch
+    from paper_1903_02581_amd import Propagator
+    from paper_1903_02581_amd.autograd import bunching_loss, saddle_potential
+    w = _case(12, 12, 8)
+    announce("autograd BunchingLoss 12x12 steps=8")
+    x = torch.tensor(-0.5 * w.lx + np.arange(w.nx) * (w.lx / w.nx), dtype=torch.float64)
+    y = torch.tensor(-0.5 * w.ly + np.arange(w.ny) * (w.ly / w.ny), dtype=torch.float64)
+    p = Propagator.from_workload(w)
+
+    def loss_of(th, b):
+        v = saddle_potential(th, x, y, w.ly)
+        return bunching_loss(v, b, p, w.psi_a, w.psi_b, steps=w.steps, w_top=w.w_top,
+                             ckpt_every=3)
+
+    th = torch.tensor([w.v0, w.v1, w.sx, w.sy], dtype=torch.float64, requires_grad=True)
+    b = torch.tensor(w.b_tesla, dtype=torch.float64, requires_grad=True)
+    L = loss_of(th, b)
+    L.backward()
+    grads = np.concatenate([th.grad.numpy(), [b.grad.item()]])
+    base = np.array([w.v0, w.v1, w.sx, w.sy, w.b_tesla])
+    fd = np.empty(5)
+    for i in range(5):
+        h = 1e-4 * abs(base[i])
+        vals = []
+        for s in (+1, -1):
+            t = base.copy()
+            t[i] += s * h
+            with torch.no_grad():
+                vals.append(float(loss_of(torch.tensor(t[:4]), torch.tensor(t[4]))))
+        fd[i] = (vals[0] - vals[1]) / (2 * h)
+    for a, f in zip(grads, fd):
+        assert abs(a - f) <= 1e-6 * max(abs(f), 1e-9), (grads, fd)
+    p.close()

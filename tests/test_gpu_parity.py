@@ -1,0 +1,186 @@
+"""GPU path (libhom4d.so through the C ABI) against the FP64 CPU oracle.
+
+Bar: relative L2 error of the final state <= 1e-10 for the FP64 path and
+<= 1e-4 for the mixed (complex64-storage) path; observables compared too.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import preset
+from workloads.presets import build
+from tests.gpu_util import announce, gpu_run, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-4
+
+
+def test_tiny_fp64_full_run():
+    w = preset("tiny")
+    announce(f"tiny fp64 {w.nx}x{w.ny} steps={w.steps}")
+    psi, obs = gpu_run(w, w.steps)
+    ref, _ = oracle_run(w, w.steps)
+    assert rel_l2(psi, ref) <= FP64_TOL
+    ro = O.observables(ref, w.w_top)
+    for k in ("norm", "p_tt", "p_tb", "p_bt", "p_bb", "p_b", "p_ab"):
+        assert abs(obs[k] - ro[k]) <= 1e-12, (k, obs[k], ro[k])
+    assert obs["step"] == w.steps
+
+
+# every supported line length appears on the x axes and on the y axes; (n, m) pairs keep
+# the 4D state near 1e6 points so the oracle stays fast
+SIZES = [(4, 6), (6, 4), (8, 12), (12, 8), (16, 24), (24, 16), (32, 12), (12, 32),
+         (48, 16), (16, 48), (64, 8), (8, 64), (96, 8), (8, 96), (128, 4), (4, 128),
+         (256, 4), (4, 256)]
+
+
+@pytest.mark.parametrize("nx,ny", SIZES)
+def test_sizes_fp64(nx, ny):
+    w = build("sz", nx, ny, 10.0 * nx, 12.0 * ny, b_tesla=5.0, dt_fs=2.0, steps=4,
+              sigma_x=max(10.0, 2.0 * nx), seed=nx + ny)
+    announce(f"sizes fp64 {nx}x{ny} steps={w.steps}")
+    psi, obs = gpu_run(w, w.steps)
+    ref, _ = oracle_run(w, w.steps)
+    assert rel_l2(psi, ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (48, 16), (16, 96)])
+def test_sizes_mixed(nx, ny):
+    w = build("szm", nx, ny, 10.0 * nx, 12.0 * ny, b_tesla=5.0, dt_fs=2.0, steps=20,
+              sigma_x=20.0, seed=3)
+    announce(f"sizes mixed {nx}x{ny} steps={w.steps}")
+    psi, obs = gpu_run(w, w.steps, precision="mixed")
+    ref, _ = oracle_run(w, w.steps)
+    assert rel_l2(psi, ref) <= MIXED_TOL
+    ro = O.observables(ref, w.w_top)
+    assert abs(obs["p_b"] - ro["p_b"]) <= MIXED_TOL
+
+
+def test_tiny_mixed_full_run():
+    w = preset("tiny")
+    announce(f"tiny mixed steps={w.steps}")
+    psi, obs = gpu_run(w, w.steps, precision="mixed")
+    ref, _ = oracle_run(w, w.steps)
+    err = rel_l2(psi, ref)
+    ro = O.observables(ref, w.w_top)
+    announce(f"tiny mixed rel_l2={err:.3e} dPb={abs(obs['p_b'] - ro['p_b']):.3e} "
+             f"dnorm={abs(obs['norm'] - ro['norm']):.3e}")
+    assert err <= MIXED_TOL
+    assert abs(obs["p_b"] - ro["p_b"]) <= MIXED_TOL
+    assert abs(obs["norm"] - ro["norm"]) <= MIXED_TOL
+
+
+def test_direct_coulomb_mode():
+    w = preset("tiny")
+    announce("tiny fp64 direct coulomb steps=50")
+    psi, _ = gpu_run(w, 50, coulomb_mode="direct")
+    ref, _ = oracle_run(w, 50)
+    assert rel_l2(psi, ref) <= FP64_TOL
+
+
+def test_screened_coulomb():
+    w = preset("tiny")
+    announce("tiny fp64 screened steps=50")
+    for mode in ("table", "direct"):
+        psi, _ = gpu_run(w, 50, coulomb_mode=mode, screen_nm=5.0)
+        ref, _ = oracle_run(w, 50, screen_nm=5.0)
+        assert rel_l2(psi, ref) <= FP64_TOL
+
+
+def test_coulomb_off():
+    w = preset("tiny", coulomb_c=0.0)
+    announce("tiny fp64 coulomb off steps=50")
+    psi, _ = gpu_run(w, 50)
+    ref, _ = oracle_run(w, 50)
+    assert rel_l2(psi, ref) <= FP64_TOL
+
+
+@pytest.mark.parametrize("sym", [1, 0])
+def test_symmetric_and_product_states(sym):
+    w = preset("tiny")
+    announce(f"tiny fp64 sym={sym} steps=50")
+    psi, obs = gpu_run(w, 50, sym=sym)
+    ref, _ = oracle_run(w, 50, sym=sym)
+    assert rel_l2(psi, ref) <= FP64_TOL
+    ro = O.observables(ref, w.w_top)
+    assert abs(obs["p_b"] - ro["p_b"]) <= 1e-12
+
+
+def test_zero_steps_is_identity_and_init_matches():
+    w = preset("tiny")
+    announce("init only")
+    psi, obs = gpu_run(w, 0)
+    ref = O.init_state(w.psi_a, w.psi_b, -1)
+    assert rel_l2(psi, ref) <= 1e-14
+    assert abs(obs["norm"] - 1.0) <= 1e-13
+
+
+def test_entanglement_and_slice():
+    from paper_1903_02581_amd import Propagator
+    w = preset("tiny")
+    announce("entanglement tiny")
+    p = Propagator.from_workload(w)
+    p.step(40)
+    psi = p.store_state()
+    y = -0.5 * w.ly + np.arange(w.ny) * (w.ly / w.ny)
+    j1 = int(np.argmin(np.abs(y - 11.5)))
+    j2 = int(np.argmin(np.abs(y + 11.5)))
+    ix = np.arange(w.nx)
+    s_gpu = p.entanglement(ix, j1, ix, j2)
+    s_ref = O.entanglement(psi, ix, j1, ix, j2)
+    assert abs(s_gpu - s_ref) <= 1e-10
+    sl = p.gather_slice(ix[::2], j1, ix[1::3], j2)
+    assert np.array_equal(sl, psi[ix[::2], j1][:, ix[1::3], j2])
+    p.close()
+
+
+def test_load_store_roundtrip_and_determinism():
+    from paper_1903_02581_amd import Propagator
+    w = preset("tiny")
+    announce("load/store + determinism")
+    rng = np.random.default_rng(0)
+    n = (w.nx * w.ny) ** 2
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    for prec in ("fp64", "mixed"):
+        p = Propagator.from_workload(w, precision=prec)
+        p.load_state(x)
+        back = p.store_state().ravel()
+        if prec == "fp64":
+            assert np.array_equal(back, x)
+        else:
+            assert np.array_equal(back, x.astype(np.complex64).astype(np.complex128))
+        p.close()
+    a, _ = gpu_run(w, 30)
+    b, _ = gpu_run(w, 30)
+    assert np.array_equal(a, b)
+
+
+def test_watchdog_and_errors():
+    from paper_1903_02581_amd import Propagator, Hom4dError
+    w = preset("tiny")
+    announce("watchdog and error paths")
+    p = Propagator.from_workload(w)
+    n = (w.nx * w.ny) ** 2
+    bad = np.zeros(n, complex)
+    bad[5] = np.nan
+    p.load_state(bad)
+    o = p.observables(w.w_top)
+    assert o["status"] == -6
+    with pytest.raises(Hom4dError):
+        p.step(-1)
+    with pytest.raises(Hom4dError):
+        p.observables(np.full((w.nx, w.ny), 2.0))
+    with pytest.raises(Hom4dError):
+        p.entanglement([0, 99], 0, [0], 0)
+    with pytest.raises(Hom4dError):
+        p.init_state(w.psi_a, w.psi_a, -1)      # antisymmetrised identical orbitals: zero norm
+    with pytest.raises(Hom4dError):
+        p.grad_backward(w.w_top)                 # no recording
+    p.init_state(w.psi_a, w.psi_b, -1)
+    p.step(3)
+    p.set_norm_tol(1e-300)
+    with pytest.raises(Hom4dError):
+        p.observables(w.w_top, check=True)
+    p.close()
