@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Throughput of the two-electron split-step propagator on one MI355X.
+
+Workload (default): the 64x64-per-electron FP64 case -- 16.8M complex128 grid
+points (268 MB), box 800 x 600 nm, GaAs (m* = 0.067, eps_r = 12.9), B = 5 T,
+dt = 2 fs, 2000 Strang steps, softened Coulomb (d = 2 nm), saddle QPC with
+the first (V0, sigma_x) of the seeded 9-run sweep.  Synthetic, seeded inputs.
+
+A step is one Strang step S(dt) of the whole hot path: two x passes, the y1
+pass with the potential factor, the y2 pass with the potential factor
+(Sec. II.C Eq. (evoloperat) of arXiv 1903.02581), with the region
+probabilities (Eq. (p_bunching)) sampled every 100 steps inside the timed
+region.  value = grid-point-steps per second = (nx ny)^2 * steps / time.
+
+Extra objects on the JSON line:
+  roofline     -- the dominant pass kernel, timed with HIP events on the
+                  library's stream, against the 8 TB/s HBM peak;
+  cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same workload;
+  mixed        -- the complex64-storage form on the same workload and its error
+                  against the FP64 GPU run (|dP_b|, relative L2 of psi, norm).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+AXES = {0: "x1", 1: "y1", 2: "x2", 3: "y2"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mid.json")
+KERNEL_SOURCES = ["paper_1903_02581_amd/csrc/axis_pass.hpp", "paper_1903_02581_amd/csrc/dft_regs.hpp",
+                  "paper_1903_02581_amd/csrc/hom4d_host.cpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def make_prop(w, precision):
+    from paper_1903_02581_amd import Propagator
+    return Propagator.from_workload(w, precision=precision)
+
+
+def timed_run(prop, w, steps, warmup, sample_every):
+    import torch
+    prop.step(warmup)
+    torch.cuda.synchronize()
+    samples = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(sample_every, steps - done) if sample_every else steps
+        prop.step(k)
+        done += k
+        if sample_every:
+            o = prop.observables(w.w_top)
+            samples.append((o["step"], o["p_b"], o["norm"]))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, samples
+
+
+def pass_timing(prop, reps=20):
+    """Average duration of each of the four pass kernels, HIP events on the library stream."""
+    import torch
+    out = {}
+    stream = prop.stream
+    for axis in range(4):
+        prop.run_pass(axis, 3)
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        prop.run_pass(axis, reps)
+        end.record(stream)
+        end.synchronize()
+        out[AXES[axis]] = start.elapsed_time(end) / reps * 1e-3   # seconds per launch
+    return out
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle, as it stands, on the first steps of the same workload."""
+    import oracle as O
+    g = O.make_grid(w.nx, w.ny, w.lx, w.ly, b_tesla=w.b_tesla, soft_nm=w.soft_nm,
+                    coulomb_c=w.coulomb_c, mstar_rel=w.mstar_rel, eps_r=w.eps_r)
+    psi = O.init_state(w.psi_a, w.psi_b, w.sym)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        psi = O.strang_step(psi, g, w.v_table, w.dt_fs)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return n, el
+
+
+def read_traffic(nbytes_alg):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--sample-every", type=int, default=100)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--profile-passes", type=int, default=0,
+                    help="only launch each pass kernel this many times (for counter runs)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from workloads import preset
+
+    w = preset("mid", run=0)
+    P = w.points
+    if args.profile_passes:
+        prop = make_prop(w, args.precision)
+        for axis in range(4):
+            prop.run_pass(axis, args.profile_passes)
+        torch.cuda.synchronize()
+        # a plain copy of known size for calibrating the HBM byte counters
+        src = torch.empty(P * 2, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_passes": args.profile_passes, "copy_bytes": src.numel() * 8}))
+        return
+
+    prop = make_prop(w, args.precision)
+    sec, samples = timed_run(prop, w, args.steps, args.warmup, args.sample_every)
+    value = P * args.steps / sec
+    psi64_final = None
+    obs64 = prop.observables(w.w_top)
+    if args.precision == "fp64" and not args.no_mixed:
+        psi64_final = prop.store_state()
+
+    passes = pass_timing(prop)
+    dom = max(passes, key=passes.get)
+    sbytes = 16 if args.precision == "fp64" else 8
+    alg_bytes = 2 * sbytes * P                 # one read + one write of the state per launch
+    achieved = alg_bytes / passes[dom] / 1e9
+    traffic = read_traffic(alg_bytes)
+    prop.close()
+
+    mixed = None
+    if args.precision == "fp64" and not args.no_mixed:
+        pm = make_prop(w, "mixed")
+        sec_m, samples_m = timed_run(pm, w, args.steps, args.warmup, args.sample_every)
+        om = pm.observables(w.w_top)       # same trajectory as the FP64 run: warmup + steps
+        psi_m = pm.store_state()
+        passes_m = pass_timing(pm)
+        pm.close()
+        dpb = [abs(a[1] - b[1]) for a, b in zip(samples, samples_m)]
+        mixed = {
+            "value": P * args.steps / sec_m, "unit": "gp-steps/s", "dtype": "c64 storage, f64 arithmetic",
+            "speedup_vs_fp64": (P * args.steps / sec_m) / value,
+            "err_vs_fp64_gpu": {
+                "abs_dP_b_final": abs(om["p_b"] - obs64["p_b"]),
+                "abs_dP_b_max_sampled": max(dpb) if dpb else None,
+                "rel_l2_psi_final": float(np.linalg.norm(psi_m - psi64_final) / np.linalg.norm(psi64_final)),
+                "abs_dnorm_final": abs(om["norm"] - obs64["norm"]),
+            },
+            "pass_seconds": passes_m,
+        }
+
+    cpu = None
+    if not args.no_cpu:
+        n_cpu, t_cpu = cpu_baseline(w, args.cpu_budget)
+        cpu = {"value": P * n_cpu / t_cpu, "unit": "gp-steps/s", "cores": os.cpu_count(),
+               "kind": "oracle",
+               "sample": f"first {n_cpu} Strang steps of the same 64x64 workload, FP64 numpy/scipy "
+                         f"(scipy.fft workers={os.cpu_count()}), {t_cpu:.1f} s"}
+
+    line = {
+        "metric": "4D grid-point-steps/s (FP64 split-step, 64x64 per electron)",
+        "value": value,
+        "unit": "gp-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "c64-storage/f64",
+        "data": "synthetic",
+        "config": {"workload": "mid: 64x64 grid per electron (16.8M complex128 points), 800x600 nm, "
+                               "GaAs, B=5T, dt=2fs, softened Coulomb d=2nm, sweep run 0",
+                   "nx": w.nx, "ny": w.ny, "points": P, "precision": args.precision,
+                   "observables_every": args.sample_every, "final_p_b": obs64["p_b"],
+                   "final_norm": obs64["norm"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (traffic["bytes_per_launch"][dom] if traffic else None),
+                     "kernel": f"k_axis pass along {dom}", "algorithmic_bytes_per_launch": alg_bytes,
+                     "avg_launch_s": passes[dom], "pass_seconds": passes},
+        "cpu_baseline": cpu,
+        "mixed": mixed,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

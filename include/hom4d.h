@@ -178,6 +178,15 @@ int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs,
 /* Abandon an open recording. */
 int hom4d_grad_end(hom4d* h);
 
+/* Measurement entry point: launch one fused pass reps times on the bound
+ * state, asynchronously.  axis: 0 = x1 and 2 = x2 (kinetic x factor of a full
+ * dt), 1 = y1 (potential factor, then kinetic y factor), 3 = y2 (kinetic y
+ * factor, then potential factor) -- the four kernels one step is made of
+ * (Sec. II.C Eq. (evoloperat)).  Each launch applies a unitary factor, so the
+ * state stays normalised but no longer follows the step sequence; the step
+ * count is not changed. */
+int hom4d_run_pass(hom4d* h, int32_t axis, int32_t reps);
+
 /* Static string for a status code. */
 const char* hom4d_strerror(int status);
 

@@ -825,6 +825,21 @@ int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs, voi
     return HOM4D_OK;
 }
 
+int hom4d_run_pass(hom4d* h, int32_t axis, int32_t reps) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (axis < 0 || axis > 3) return fail(HOM4D_EINVAL, "axis=%d must be 0..3", axis);
+    if (reps < 0) return fail(HOM4D_EINVAL, "reps=%d must be >= 0", reps);
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    if (!h->have_v) return fail(HOM4D_ESTATE, "no potential set (hom4d_set_potential)");
+    const KTab kt = (axis == AX_X1 || axis == AX_X2) ? KX_FULL : KY_FULL;
+    const int vmode = axis == AX_Y1 ? 1 : (axis == AX_Y2 ? 2 : 0);
+    for (int32_t r = 0; r < reps; ++r) {
+        int rc = run_pass(h, axis, kt, vmode, 1, nullptr, false, 0, nullptr);
+        if (rc) return rc;
+    }
+    return HOM4D_OK;
+}
+
 const char* hom4d_strerror(int status) {
     switch (status) {
         case HOM4D_OK: return "ok";

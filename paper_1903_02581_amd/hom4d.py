@@ -29,7 +29,8 @@ EXPORTS = ["hom4d_create", "hom4d_destroy", "hom4d_validate_cfg", "hom4d_state_b
            "hom4d_bind_state", "hom4d_set_potential", "hom4d_set_field", "hom4d_init_state",
            "hom4d_load_state", "hom4d_store_state", "hom4d_step", "hom4d_observables",
            "hom4d_set_norm_tol", "hom4d_entanglement", "hom4d_gather_slice", "hom4d_grad_begin",
-           "hom4d_grad_backward", "hom4d_grad_end", "hom4d_strerror", "hom4d_last_error"]
+           "hom4d_grad_backward", "hom4d_grad_end", "hom4d_run_pass", "hom4d_strerror",
+           "hom4d_last_error"]
 
 
 class HomCfg(ctypes.Structure):
@@ -84,6 +85,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "hom4d_grad_begin": ([vp, c_int32, vp, c_size_t], c_int),
         "hom4d_grad_backward": ([vp, dp, dp, vp, dp, dp, dp], c_int),
         "hom4d_grad_end": ([vp], c_int),
+        "hom4d_run_pass": ([vp, c_int32, c_int32], c_int),
         "hom4d_strerror": ([c_int], ctypes.c_char_p),
         "hom4d_last_error": ([], ctypes.c_char_p),
     }
@@ -211,7 +213,7 @@ class Propagator:
         w = np.ascontiguousarray(np.asarray(w_top, dtype=np.float64)).reshape(self.nx, self.ny)
         o = HomObs()
         rc = self.lib.hom4d_observables(self.h, _dptr(w), byref(o))
-        if rc != 0 and (check or rc not in (-7,)):
+        if rc != 0 and (check or rc not in (-6, -7)):
             self._check(rc, "observables")
         return dict(norm=o.norm, p_tt=o.p_tt, p_tb=o.p_tb, p_bt=o.p_bt, p_bb=o.p_bb, p_b=o.p_b,
                     p_ab=o.p_ab, step=int(o.step), status=int(rc))
@@ -268,6 +270,10 @@ class Propagator:
                                                  c_void_p(self._lam.data_ptr()), byref(loss),
                                                  _dptr(dldv), byref(dldb)), "grad_backward")
         return float(loss.value), dldv, float(dldb.value)
+
+    def run_pass(self, axis: int, reps: int = 1):
+        """Launch one of the four fused pass kernels reps times (measurement only)."""
+        self._check(self.lib.hom4d_run_pass(self.h, int(axis), int(reps)), "run_pass")
 
     def grad_end(self):
         self._check(self.lib.hom4d_grad_end(self.h), "grad_end")

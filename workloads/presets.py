@@ -101,8 +101,9 @@ def saddle_potential(x: np.ndarray, y: np.ndarray, v0: float, v1: float,
     X = x[:, None]
     Y = y[None, :]
     yw = WALL_POS_FRAC * ly
-    walls = WALL_HEIGHT_MEV * (1.0 / (1.0 + np.exp((yw - Y) / WALL_SMOOTH_NM))
-                               + 1.0 / (1.0 + np.exp((yw + Y) / WALL_SMOOTH_NM)))
+    with np.errstate(over="ignore"):   # exp overflow -> inf -> the wall term is exactly 0
+        walls = WALL_HEIGHT_MEV * (1.0 / (1.0 + np.exp((yw - Y) / WALL_SMOOTH_NM))
+                                   + 1.0 / (1.0 + np.exp((yw + Y) / WALL_SMOOTH_NM)))
     return v0 * np.exp(-X ** 2 / sx ** 2) - v1 * np.exp(-Y ** 2 / sy ** 2) + walls
 
 
