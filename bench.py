@@ -35,10 +35,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-AXES = {0: "x1", 1: "y1", 2: "x2", 3: "y2"}
+AXES = {0: "x1", 1: "y1", 2: "x2", 3: "y2", 4: "plane(x2,V,y2)", 5: "y1+V"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mid.json")
 KERNEL_SOURCES = ["paper_1903_02581_amd/csrc/axis_pass.hpp", "paper_1903_02581_amd/csrc/dft_regs.hpp",
-                  "paper_1903_02581_amd/csrc/hom4d_host.cpp"]
+                  "paper_1903_02581_amd/csrc/plane_pass.hpp", "paper_1903_02581_amd/csrc/hom4d_host.cpp"]
 
 
 def kernel_hash() -> str:
@@ -49,9 +49,14 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+PLAN = 0
+
+
 def make_prop(w, precision):
     from paper_1903_02581_amd import Propagator
-    return Propagator.from_workload(w, precision=precision)
+    p = Propagator.from_workload(w, precision=precision)
+    p.set_pass_plan(PLAN)
+    return p
 
 
 def timed_run(prop, w, steps, warmup, sample_every):
@@ -72,12 +77,13 @@ def timed_run(prop, w, steps, warmup, sample_every):
     return time.perf_counter() - t0, samples
 
 
-def pass_timing(prop, reps=20):
+def pass_timing(prop, reps=50):
     """Average duration of each of the four pass kernels, HIP events on the library stream."""
     import torch
     out = {}
     stream = prop.stream
-    for axis in range(4):
+    axes = (0, 4, 5) if prop.passes_per_step == 3 else (0, 1, 2, 3)
+    for axis in axes:
         prop.run_pass(axis, 3)
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
@@ -127,6 +133,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--plan", type=int, default=0, choices=[0, 1],
+                    help="0: fused three-pass steps (default), 1: four per-axis passes")
     ap.add_argument("--profile-passes", type=int, default=0,
                     help="only launch each pass kernel this many times (for counter runs)")
     args = ap.parse_args()
@@ -138,12 +146,15 @@ def main():
 
     import torch
     from workloads import preset
+    global PLAN
+    PLAN = args.plan
 
     w = preset("mid", run=0)
     P = w.points
     if args.profile_passes:
         prop = make_prop(w, args.precision)
-        for axis in range(4):
+        axes = (0, 4, 5) if prop.passes_per_step == 3 else (0, 1, 2, 3)
+        for axis in axes:
             prop.run_pass(axis, args.profile_passes)
         torch.cuda.synchronize()
         # a plain copy of known size for calibrating the HBM byte counters
@@ -162,6 +173,7 @@ def main():
     if args.precision == "fp64" and not args.no_mixed:
         psi64_final = prop.store_state()
 
+    passes_per_step = prop.passes_per_step
     passes = pass_timing(prop)
     dom = max(passes, key=passes.get)
     sbytes = 16 if args.precision == "fp64" else 8
@@ -215,12 +227,13 @@ def main():
         "config": {"workload": "mid: 64x64 grid per electron (16.8M complex128 points), 800x600 nm, "
                                "GaAs, B=5T, dt=2fs, softened Coulomb d=2nm, sweep run 0",
                    "nx": w.nx, "ny": w.ny, "points": P, "precision": args.precision,
-                   "observables_every": args.sample_every, "final_p_b": obs64["p_b"],
+                   "observables_every": args.sample_every, "passes_per_step": passes_per_step,
+                   "final_p_b": obs64["p_b"],
                    "final_norm": obs64["norm"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (traffic["bytes_per_launch"][dom] if traffic else None),
-                     "kernel": f"k_axis pass along {dom}", "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel": f"pass kernel {dom}", "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_s": passes[dom], "pass_seconds": passes},
         "cpu_baseline": cpu,
         "mixed": mixed,

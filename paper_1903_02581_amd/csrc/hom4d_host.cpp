@@ -182,6 +182,7 @@ struct hom4d {
     int64_t step = 0;
     bool have_v = false;
     double norm_tol = 1e-6;
+    int pass_plan = 0;           // 0: fused plane pass where built, 1: per-axis passes only
     // gradient recording
     bool rec = false;
     int ckpt_every = 0;
@@ -331,9 +332,52 @@ int run_pass(hom4d* h, int axis, KTab kt, int vmode, int nst, void* lam, bool re
     return sync_check(h, "axis pass");
 }
 
+// The fused (x2, y2) plane pass: X2(kt), potential factor, Y2(dt).
+int run_plane(hom4d* h, KTab kt) {
+    const hom4d_cfg& c = h->cfg;
+    if (!h->have_v) return fail(HOM4D_ESTATE, "no potential set (hom4d_set_potential)");
+    PassArgs a{};
+    a.psi = h->psi;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.tw = h->tw_x;
+    a.ktab = kt == KX_HALF ? h->kx_half : h->kx_full;
+    a.tw2 = h->tw_y;
+    a.ktab2 = h->ky_full;
+    a.a1 = h->a1_half;
+    a.ac = (c.coulomb_c != 0.0) ? h->ac_half : nullptr;
+    a.vdirect = c.coulomb_mode == HOM4D_COULOMB_DIRECT ? 1 : 0;
+    a.vtab = h->v_dev;
+    a.vscale = 0.5 * c.dt_fs / h->u.hbar;
+    a.dx = c.lx_nm / c.nx;
+    a.dy = c.ly_nm / c.ny;
+    a.soft2 = c.soft_nm * c.soft_nm;
+    a.ck = c.coulomb_c * h->u.kc;
+    a.inv_screen = c.screen_nm > 0.0 ? 1.0 / c.screen_nm : 0.0;
+    HIP_TRY(launch_plane(c.nx, c.ny, h->mixed, a, h->stream));
+    return sync_check(h, "plane pass");
+}
+
+bool use_plane(const hom4d* h) { return h->pass_plan == 0 && plane_available(h->cfg.nx, h->cfg.ny, h->mixed); }
+
+// n whole forward steps in three passes per step:
+//   X1 | [X2, V, Y2] (plane) | [Y1, V]  ...  closing X1, X2 halves.
+int run_steps_plane(hom4d* h, int64_t n) {
+    int rc;
+    if ((rc = run_pass(h, AX_X1, KX_HALF, 0, 1, nullptr, false, 0, nullptr))) return rc;
+    for (int64_t i = 0; i < n; ++i) {
+        const bool last = i == n - 1;
+        if ((rc = run_plane(h, i == 0 ? KX_HALF : KX_FULL))) return rc;
+        if ((rc = run_pass(h, AX_Y1, KY_FULL, 2, 1, nullptr, false, 0, nullptr))) return rc;
+        if ((rc = run_pass(h, AX_X1, last ? KX_HALF : KX_FULL, 0, 1, nullptr, false, 0, nullptr))) return rc;
+    }
+    return run_pass(h, AX_X2, KX_HALF, 0, 1, nullptr, false, 0, nullptr);
+}
+
 // n whole steps with merged X halves; the state is closed at the end.
 int run_steps(hom4d* h, int64_t n, int nst, void* lam, bool reverse, const GradCtx* g) {
     if (n <= 0) return HOM4D_OK;
+    if (nst == 1 && !reverse && use_plane(h)) return run_steps_plane(h, n);
     const bool gr = nst == 2;
     int rc;
     if ((rc = run_pass(h, AX_X1, KX_HALF, 0, nst, lam, reverse, gr ? G_GB : 0, g))) return rc;
@@ -825,9 +869,30 @@ int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs, voi
     return HOM4D_OK;
 }
 
+int hom4d_set_pass_plan(hom4d* h, int32_t plan) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (plan != 0 && plan != 1) return fail(HOM4D_EINVAL, "plan=%d must be 0 or 1", plan);
+    h->pass_plan = plan;
+    return HOM4D_OK;
+}
+
+int hom4d_pass_plan(hom4d* h) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    return use_plane(h) ? 3 : 4;
+}
+
 int hom4d_run_pass(hom4d* h, int32_t axis, int32_t reps) {
     if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
-    if (axis < 0 || axis > 3) return fail(HOM4D_EINVAL, "axis=%d must be 0..3", axis);
+    if (axis < 0 || axis > 5) return fail(HOM4D_EINVAL, "axis=%d must be 0..5", axis);
+    if (axis >= 4) {
+        if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+        if (axis == 4 && !use_plane(h)) return fail(HOM4D_EINVAL, "no fused plane pass for this size/precision");
+        for (int32_t r = 0; r < reps; ++r) {
+            int rc = axis == 4 ? run_plane(h, KX_FULL) : run_pass(h, AX_Y1, KY_FULL, 2, 1, nullptr, false, 0, nullptr);
+            if (rc) return rc;
+        }
+        return HOM4D_OK;
+    }
     if (reps < 0) return fail(HOM4D_EINVAL, "reps=%d must be >= 0", reps);
     if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
     if (!h->have_v) return fail(HOM4D_ESTATE, "no potential set (hom4d_set_potential)");

@@ -27,6 +27,8 @@ struct PassArgs {
     int kconj;                // use conj(ktab) and conj(potential factor): reverse sweep
     const double2* tw;        // twiddles exp(-2 pi i j / n), j < n
     const double2* ktab;      // k-space factor incl. 1/n: [ny][nx] for x axes, [ny] for y axes
+    const double2* tw2;       // plane pass only: twiddles of the y lines
+    const double2* ktab2;     // plane pass only: y kinetic factor [ny]
     int vmode;                // 0: none, 1: potential factor before the transform, 2: after
     // potential factor, table form
     const double2* a1;        // [nx*ny]  exp(-i tau V(x,y)/hbar)
@@ -56,6 +58,12 @@ bool fft_shape(int n, FftShape* out);
 // Launch one per-axis pass: blocks of t*W threads, nlines/W blocks.
 hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, int64_t nlines,
                        size_t lds_bytes, hipStream_t s);
+
+// Fused (x2, y2)-plane pass: X2(ktab) -> potential factor -> Y2(ktab2), one
+// workgroup per electron-1 position.  Returns hipErrorInvalidValue when no
+// kernel is built for (nx, ny, storage); plane_available() says beforehand.
+bool plane_available(int nx, int ny, bool mixed);
+hipError_t launch_plane(int nx, int ny, bool mixed, const PassArgs& a, hipStream_t s);
 
 // Reductions and elementwise kernels.
 hipError_t launch_init_norm(const double2* pa, const double2* pb, int sym, int nxy, double* part,

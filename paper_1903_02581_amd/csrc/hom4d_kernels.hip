@@ -32,6 +32,8 @@ AxisKernel pick_axis_f64_1(int axis, int n, int* t);
 AxisKernel pick_axis_f64_2(int axis, int n, int* t);
 AxisKernel pick_axis_f32_1(int axis, int n, int* t);
 AxisKernel pick_axis_f32_2(int axis, int n, int* t);
+AxisKernel pick_plane_f64(int nx, int ny, int* nt);
+AxisKernel pick_plane_f32(int nx, int ny, int* nt);
 
 namespace {
 
@@ -206,6 +208,19 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
     const int64_t nblocks = nlines / a.W;
     if (nblocks > 0x7fffffff || t * a.W > 256) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3(t * a.W), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+bool plane_available(int nx, int ny, bool mixed) {
+    int nt = 0;
+    return (mixed ? pick_plane_f32(nx, ny, &nt) : pick_plane_f64(nx, ny, &nt)) != nullptr;
+}
+
+hipError_t launch_plane(int nx, int ny, bool mixed, const PassArgs& a, hipStream_t s) {
+    int nt = 0;
+    AxisKernel fn = mixed ? pick_plane_f32(nx, ny, &nt) : pick_plane_f64(nx, ny, &nt);
+    if (!fn || nt <= 0 || nt > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3((unsigned)(nx * ny)), dim3(nt), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,38 @@
+// Instantiations of the fused (x2, y2)-plane pass for float2 storage.
+#include "plane_pass.hpp"
+
+namespace hom4d_impl {
+namespace {
+using dev::AxisKernel;
+using dev::k_plane2;
+using dev::plane_threads;
+using dev::Shape;
+
+template <int NX, int NY>
+AxisKernel mk(int* nt) {
+    constexpr int T = plane_threads(NX, NY, Shape<NX>::t, Shape<NY>::t);
+    *nt = T;
+    return k_plane2<float2, NX, NY, T>;
+}
+}  // namespace
+
+AxisKernel pick_plane_f32(int nx, int ny, int* nt) {
+#define HOM4D_PLANE(X, Y) \
+    if (nx == X && ny == Y) return mk<X, Y>(nt);
+    HOM4D_PLANE(16, 16)
+    HOM4D_PLANE(24, 24)
+    HOM4D_PLANE(32, 32)
+    HOM4D_PLANE(48, 48)
+    HOM4D_PLANE(64, 64)
+    HOM4D_PLANE(96, 64)
+    HOM4D_PLANE(64, 96)
+    HOM4D_PLANE(96, 96)
+    HOM4D_PLANE(128, 64)
+    HOM4D_PLANE(64, 128)
+    HOM4D_PLANE(48, 16)
+    HOM4D_PLANE(16, 48)
+#undef HOM4D_PLANE
+    *nt = 0;
+    return nullptr;
+}
+}  // namespace hom4d_impl

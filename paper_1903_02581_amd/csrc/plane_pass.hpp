@@ -1,0 +1,318 @@
+// Fused pass over the contiguous (x2, y2) plane of one electron-1 position.
+//
+// For fixed r1 = (x1, y1) the nx*ny values Psi(r1, x2, y2) are contiguous in
+// the [x1][y1][x2][y2] layout.  One workgroup owns one such plane and applies,
+// in one HBM read and one HBM write,
+//     X2(tau):  transform along x2, kinetic phase of (k_x2, y2), inverse,
+//     V(dt/2):  exp(-i dt/2 (V(r1) + V(r2) + V12(r1 - r2)) / hbar),
+//     Y2(dt):   transform along y2, kinetic phase of k_y2, inverse,
+// i.e. three consecutive factors of the Strang step (arXiv 1903.02581,
+// Sec. II.C Eq. (evoloperat); the x and y kinetic terms of Appendix A).  The
+// plane stays in LDS (FP64) between the stages; each line transform is the
+// same register/LDS four-step network as the per-axis pass.
+#pragma once
+
+#include "axis_pass.hpp"
+
+namespace hom4d_impl {
+namespace dev {
+
+template <int N>
+struct Shape;
+template <> struct Shape<4> { static constexpr int n1 = 4, n2 = 1, t = 1; };
+template <> struct Shape<6> { static constexpr int n1 = 6, n2 = 1, t = 1; };
+template <> struct Shape<8> { static constexpr int n1 = 8, n2 = 1, t = 1; };
+template <> struct Shape<12> { static constexpr int n1 = 12, n2 = 1, t = 1; };
+template <> struct Shape<16> { static constexpr int n1 = 4, n2 = 4, t = 4; };
+template <> struct Shape<24> { static constexpr int n1 = 12, n2 = 2, t = 2; };
+template <> struct Shape<32> { static constexpr int n1 = 8, n2 = 4, t = 4; };
+template <> struct Shape<48> { static constexpr int n1 = 12, n2 = 4, t = 4; };
+template <> struct Shape<64> { static constexpr int n1 = 8, n2 = 8, t = 8; };
+template <> struct Shape<96> { static constexpr int n1 = 12, n2 = 8, t = 4; };
+template <> struct Shape<128> { static constexpr int n1 = 16, n2 = 8, t = 8; };
+
+template <class S, int NX, int NY, int NT>
+__global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
+    using SX_ = Shape<NX>;
+    using SY_ = Shape<NY>;
+    constexpr int A1 = SX_::n1, A2 = SX_::n2, TX = SX_::t;
+    constexpr int B1 = SY_::n1, B2 = SY_::n2, TY = SY_::t;
+    constexpr int EX = NX / TX, EY = NY / TY;
+    constexpr int JAX = A2 / TX, IBX = A1 / TX;
+    constexpr int JAY = B2 / TY, IBY = B1 / TY;
+    constexpr int LDP = NY + 1;                   // padded row of the plane in LDS
+    constexpr int SLX = NY * TX, QX = (SLX + NT - 1) / NT;
+    constexpr int SLY = NX * TY, QY = (SLY + NT - 1) / NT;
+    __shared__ double2 L[NX * LDP];
+
+    const int tid = threadIdx.x;
+    const int r1 = blockIdx.x;
+    const int i1 = r1 / NY, j1 = r1 % NY;
+    S* base = reinterpret_cast<S*>(a.psi) + (int64_t)r1 * (NX * NY);
+
+    // ------------------------------------------------ X2 stage: lines along x2, one per y2
+    double2 vx[QX][EX];
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+        const int s = tid + NT * q;
+        if (s < SLX) {
+            const int c = s % NY, t = s / NY;
+#pragma unroll
+            for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                for (int n1 = 0; n1 < A1; ++n1) vx[q][jj * A1 + n1] = ld<S>(base + (n1 * A2 + t + TX * jj) * NY + c);
+#pragma unroll
+            for (int jj = 0; jj < JAX; ++jj) {
+                dft<A1, -1>(&vx[q][jj * A1]);
+                if constexpr (A2 > 1) {
+                    const int jc = t + TX * jj;
+#pragma unroll
+                    for (int k1 = 1; k1 < A1; ++k1) vx[q][jj * A1 + k1] = cmul(vx[q][jj * A1 + k1], a.tw[(jc * k1) % NX]);
+                }
+            }
+        }
+    }
+    if constexpr (A2 > 1) {
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLX) {
+                const int c = s % NY, t = s / NY;
+#pragma unroll
+                for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                    for (int k1 = 0; k1 < A1; ++k1) L[(k1 * A2 + t + TX * jj) * LDP + c] = vx[q][jj * A1 + k1];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLX) {
+                const int c = s % NY, t = s / NY;
+#pragma unroll
+                for (int ii = 0; ii < IBX; ++ii)
+#pragma unroll
+                    for (int j = 0; j < A2; ++j) vx[q][ii * A2 + j] = L[((t + TX * ii) * A2 + j) * LDP + c];
+#pragma unroll
+                for (int ii = 0; ii < IBX; ++ii) dft<A2, -1>(&vx[q][ii * A2]);
+            }
+        }
+    }
+    // kinetic x phase at (k_x2, y2)
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+        const int s = tid + NT * q;
+        if (s < SLX) {
+            const int c = s % NY, t = s / NY;
+            const double2* kt = a.ktab + (int64_t)c * NX;
+#pragma unroll
+            for (int ii = 0; ii < IBX; ++ii)
+#pragma unroll
+                for (int k2 = 0; k2 < A2; ++k2) {
+                    double2 f = kt[t + TX * ii + A1 * k2];
+                    if (a.kconj) f = conjd(f);
+                    vx[q][ii * A2 + k2] = cmul(vx[q][ii * A2 + k2], f);
+                }
+        }
+    }
+    if constexpr (A2 > 1) {
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLX)
+#pragma unroll
+                for (int ii = 0; ii < IBX; ++ii) dft<A2, 1>(&vx[q][ii * A2]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLX) {
+                const int c = s % NY, t = s / NY;
+#pragma unroll
+                for (int ii = 0; ii < IBX; ++ii)
+#pragma unroll
+                    for (int j = 0; j < A2; ++j) L[((t + TX * ii) * A2 + j) * LDP + c] = vx[q][ii * A2 + j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLX) {
+                const int c = s % NY, t = s / NY;
+#pragma unroll
+                for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                    for (int k1 = 0; k1 < A1; ++k1) vx[q][jj * A1 + k1] = L[(k1 * A2 + t + TX * jj) * LDP + c];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+        const int s = tid + NT * q;
+        if (s < SLX) {
+            const int c = s % NY, t = s / NY;
+#pragma unroll
+            for (int jj = 0; jj < JAX; ++jj) {
+                if constexpr (A2 > 1) {
+                    const int jc = t + TX * jj;
+#pragma unroll
+                    for (int k1 = 1; k1 < A1; ++k1) vx[q][jj * A1 + k1] = cmulc(vx[q][jj * A1 + k1], a.tw[(jc * k1) % NX]);
+                }
+                dft<A1, 1>(&vx[q][jj * A1]);
+            }
+            // potential factor, real space (x2 = n1 * A2 + jc, y2 = c)
+#pragma unroll
+            for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                for (int n1 = 0; n1 < A1; ++n1) {
+                    const double2 f = vfactor(a, i1, j1, n1 * A2 + t + TX * jj, c);
+                    vx[q][jj * A1 + n1] = cmul(vx[q][jj * A1 + n1], f);
+                }
+        }
+    }
+    __syncthreads();  // every X2-stage read of L is done
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+        const int s = tid + NT * q;
+        if (s < SLX) {
+            const int c = s % NY, t = s / NY;
+#pragma unroll
+            for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                for (int n1 = 0; n1 < A1; ++n1) L[(n1 * A2 + t + TX * jj) * LDP + c] = vx[q][jj * A1 + n1];
+        }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------ Y2 stage: lines along y2, one per x2
+    double2 vy[QY][EY];
+#pragma unroll
+    for (int q = 0; q < QY; ++q) {
+        const int s = tid + NT * q;
+        if (s < SLY) {
+            const int t = s % TY, row = s / TY;
+#pragma unroll
+            for (int jj = 0; jj < JAY; ++jj)
+#pragma unroll
+                for (int n1 = 0; n1 < B1; ++n1) vy[q][jj * B1 + n1] = L[row * LDP + n1 * B2 + t + TY * jj];
+#pragma unroll
+            for (int jj = 0; jj < JAY; ++jj) {
+                dft<B1, -1>(&vy[q][jj * B1]);
+                if constexpr (B2 > 1) {
+                    const int jc = t + TY * jj;
+#pragma unroll
+                    for (int k1 = 1; k1 < B1; ++k1) vy[q][jj * B1 + k1] = cmul(vy[q][jj * B1 + k1], a.tw2[(jc * k1) % NY]);
+                }
+            }
+        }
+    }
+    if constexpr (B2 > 1) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QY; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLY) {
+                const int t = s % TY, row = s / TY;
+#pragma unroll
+                for (int jj = 0; jj < JAY; ++jj)
+#pragma unroll
+                    for (int k1 = 0; k1 < B1; ++k1) L[row * LDP + k1 * B2 + t + TY * jj] = vy[q][jj * B1 + k1];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QY; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLY) {
+                const int t = s % TY, row = s / TY;
+#pragma unroll
+                for (int ii = 0; ii < IBY; ++ii)
+#pragma unroll
+                    for (int j = 0; j < B2; ++j) vy[q][ii * B2 + j] = L[row * LDP + (t + TY * ii) * B2 + j];
+#pragma unroll
+                for (int ii = 0; ii < IBY; ++ii) dft<B2, -1>(&vy[q][ii * B2]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < QY; ++q) {
+        const int s = tid + NT * q;
+        if (s < SLY) {
+            const int t = s % TY;
+#pragma unroll
+            for (int ii = 0; ii < IBY; ++ii)
+#pragma unroll
+                for (int k2 = 0; k2 < B2; ++k2) {
+                    double2 f = a.ktab2[t + TY * ii + B1 * k2];
+                    if (a.kconj) f = conjd(f);
+                    vy[q][ii * B2 + k2] = cmul(vy[q][ii * B2 + k2], f);
+                }
+        }
+    }
+    if constexpr (B2 > 1) {
+#pragma unroll
+        for (int q = 0; q < QY; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLY)
+#pragma unroll
+                for (int ii = 0; ii < IBY; ++ii) dft<B2, 1>(&vy[q][ii * B2]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QY; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLY) {
+                const int t = s % TY, row = s / TY;
+#pragma unroll
+                for (int ii = 0; ii < IBY; ++ii)
+#pragma unroll
+                    for (int j = 0; j < B2; ++j) L[row * LDP + (t + TY * ii) * B2 + j] = vy[q][ii * B2 + j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QY; ++q) {
+            const int s = tid + NT * q;
+            if (s < SLY) {
+                const int t = s % TY, row = s / TY;
+#pragma unroll
+                for (int jj = 0; jj < JAY; ++jj)
+#pragma unroll
+                    for (int k1 = 0; k1 < B1; ++k1) vy[q][jj * B1 + k1] = L[row * LDP + k1 * B2 + t + TY * jj];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < QY; ++q) {
+        const int s = tid + NT * q;
+        if (s < SLY) {
+            const int t = s % TY, row = s / TY;
+#pragma unroll
+            for (int jj = 0; jj < JAY; ++jj) {
+                if constexpr (B2 > 1) {
+                    const int jc = t + TY * jj;
+#pragma unroll
+                    for (int k1 = 1; k1 < B1; ++k1) vy[q][jj * B1 + k1] = cmulc(vy[q][jj * B1 + k1], a.tw2[(jc * k1) % NY]);
+                }
+                dft<B1, 1>(&vy[q][jj * B1]);
+            }
+#pragma unroll
+            for (int jj = 0; jj < JAY; ++jj)
+#pragma unroll
+                for (int n1 = 0; n1 < B1; ++n1) st<S>(base + row * NY + n1 * B2 + t + TY * jj, vy[q][jj * B1 + n1]);
+        }
+    }
+}
+
+// Threads per plane workgroup: enough for the larger of the two stages, at most 256.
+constexpr int plane_threads(int nx, int ny, int tx, int ty) {
+    const int s = (ny * tx > nx * ty) ? ny * tx : nx * ty;
+    const int r = ((s + 63) / 64) * 64;
+    return r > 256 ? 256 : r;
+}
+
+}  // namespace dev
+}  // namespace hom4d_impl

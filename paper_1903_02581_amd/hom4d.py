@@ -29,7 +29,8 @@ EXPORTS = ["hom4d_create", "hom4d_destroy", "hom4d_validate_cfg", "hom4d_state_b
            "hom4d_bind_state", "hom4d_set_potential", "hom4d_set_field", "hom4d_init_state",
            "hom4d_load_state", "hom4d_store_state", "hom4d_step", "hom4d_observables",
            "hom4d_set_norm_tol", "hom4d_entanglement", "hom4d_gather_slice", "hom4d_grad_begin",
-           "hom4d_grad_backward", "hom4d_grad_end", "hom4d_run_pass", "hom4d_strerror",
+           "hom4d_grad_backward", "hom4d_grad_end", "hom4d_run_pass", "hom4d_set_pass_plan",
+           "hom4d_pass_plan", "hom4d_strerror",
            "hom4d_last_error"]
 
 
@@ -86,6 +87,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "hom4d_grad_backward": ([vp, dp, dp, vp, dp, dp, dp], c_int),
         "hom4d_grad_end": ([vp], c_int),
         "hom4d_run_pass": ([vp, c_int32, c_int32], c_int),
+        "hom4d_set_pass_plan": ([vp, c_int32], c_int),
+        "hom4d_pass_plan": ([vp], c_int),
         "hom4d_strerror": ([c_int], ctypes.c_char_p),
         "hom4d_last_error": ([], ctypes.c_char_p),
     }
@@ -270,6 +273,17 @@ class Propagator:
                                                  c_void_p(self._lam.data_ptr()), byref(loss),
                                                  _dptr(dldv), byref(dldb)), "grad_backward")
         return float(loss.value), dldv, float(dldb.value)
+
+    def set_pass_plan(self, plan: int):
+        """0: fused three-pass steps where built (default); 1: four per-axis passes."""
+        self._check(self.lib.hom4d_set_pass_plan(self.h, int(plan)), "set_pass_plan")
+
+    @property
+    def passes_per_step(self) -> int:
+        rc = self.lib.hom4d_pass_plan(self.h)
+        if rc < 0:
+            self._check(rc, "pass_plan")
+        return int(rc)
 
     def run_pass(self, axis: int, reps: int = 1):
         """Launch one of the four fused pass kernels reps times (measurement only)."""
