@@ -52,9 +52,12 @@ __device__ __forceinline__ double reduce_2pi(double th) {
 }
 
 // exp(-i tau (V(r1) + V(r2) + V12(r1 - r2)) / hbar), or its conjugate.
+// VK = 1: product of the one-body and two-body factor tables; VK = 2: the FP64
+// angle evaluated here, reduced mod 2 pi, then sincos.
+template <int VK>
 __device__ __forceinline__ double2 vfactor(const PassArgs& a, int i1, int j1, int i2, int j2) {
     double2 f;
-    if (!a.vdirect) {
+    if constexpr (VK == 1) {
         f = cmul(a.a1[i1 * a.ny + j1], a.a1[i2 * a.ny + j2]);
         if (a.ac) f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)]);
         if (a.kconj) f = conjd(f);
@@ -111,7 +114,8 @@ __device__ __forceinline__ void elem_coord(int i1, int j1, int i2, int j2, int m
     c[AXIS] = m;
 }
 
-template <class S, int AXIS, int N1, int N2, int T, int NST>
+// VK: 0 = no potential factor on this pass, 1 = table form, 2 = per-point form.
+template <class S, int AXIS, int N1, int N2, int T, int NST, int VK>
 __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     constexpr int N = N1 * N2;
     constexpr int E = N / T;
@@ -187,14 +191,14 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         }
     }
 
-    if (a.vmode == 1) {
+    if (VK != 0 && a.vmode == 1) {
 #pragma unroll
         for (int jj = 0; jj < JA; ++jj) {
 #pragma unroll
             for (int n1 = 0; n1 < N1; ++n1) {
                 int c[4];
                 elem_coord<AXIS>(i1, j1, i2, j2, n1 * N2 + t + T * jj, c);
-                const double2 f = vfactor(a, c[0], c[1], c[2], c[3]);
+                const double2 f = vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
 #pragma unroll
                 for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = cmul(v[s][jj * N1 + n1], f);
             }
@@ -302,14 +306,14 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         }
     }
 
-    if (a.vmode == 2) {
+    if (VK != 0 && a.vmode == 2) {
 #pragma unroll
         for (int jj = 0; jj < JA; ++jj) {
 #pragma unroll
             for (int n1 = 0; n1 < N1; ++n1) {
                 int c[4];
                 elem_coord<AXIS>(i1, j1, i2, j2, n1 * N2 + t + T * jj, c);
-                const double2 f = vfactor(a, c[0], c[1], c[2], c[3]);
+                const double2 f = vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
 #pragma unroll
                 for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = cmul(v[s][jj * N1 + n1], f);
             }
@@ -362,32 +366,34 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
 
 using AxisKernel = void (*)(const PassArgs);
 
-template <class S, int AXIS, int NST>
+template <class S, int AXIS, int NST, int VK>
 AxisKernel pick(int n, int* t) {
     switch (n) {
-        case 4: *t = 1; return k_axis<S, AXIS, 4, 1, 1, NST>;
-        case 6: *t = 1; return k_axis<S, AXIS, 6, 1, 1, NST>;
-        case 8: *t = 1; return k_axis<S, AXIS, 8, 1, 1, NST>;
-        case 12: *t = 1; return k_axis<S, AXIS, 12, 1, 1, NST>;
-        case 16: *t = 4; return k_axis<S, AXIS, 4, 4, 4, NST>;
-        case 24: *t = 2; return k_axis<S, AXIS, 12, 2, 2, NST>;
-        case 32: *t = 4; return k_axis<S, AXIS, 8, 4, 4, NST>;
-        case 48: *t = 4; return k_axis<S, AXIS, 12, 4, 4, NST>;
-        case 64: *t = 8; return k_axis<S, AXIS, 8, 8, 8, NST>;
-        case 96: *t = 4; return k_axis<S, AXIS, 12, 8, 4, NST>;
-        case 128: *t = 8; return k_axis<S, AXIS, 16, 8, 8, NST>;
-        case 256: *t = 16; return k_axis<S, AXIS, 16, 16, 16, NST>;
+        case 4: *t = 1; return k_axis<S, AXIS, 4, 1, 1, NST, VK>;
+        case 6: *t = 1; return k_axis<S, AXIS, 6, 1, 1, NST, VK>;
+        case 8: *t = 1; return k_axis<S, AXIS, 8, 1, 1, NST, VK>;
+        case 12: *t = 1; return k_axis<S, AXIS, 12, 1, 1, NST, VK>;
+        case 16: *t = 4; return k_axis<S, AXIS, 4, 4, 4, NST, VK>;
+        case 24: *t = 2; return k_axis<S, AXIS, 12, 2, 2, NST, VK>;
+        case 32: *t = 4; return k_axis<S, AXIS, 8, 4, 4, NST, VK>;
+        case 48: *t = 4; return k_axis<S, AXIS, 12, 4, 4, NST, VK>;
+        case 64: *t = 8; return k_axis<S, AXIS, 8, 8, 8, NST, VK>;
+        case 96: *t = 4; return k_axis<S, AXIS, 12, 8, 4, NST, VK>;
+        case 128: *t = 8; return k_axis<S, AXIS, 16, 8, 8, NST, VK>;
+        case 256: *t = 16; return k_axis<S, AXIS, 16, 16, 16, NST, VK>;
         default: *t = 0; return nullptr;
     }
 }
 
+// x passes never carry the potential factor; y passes come in table and
+// per-point forms (vk = 1, 2).
 template <class S, int NST>
-AxisKernel pick_axis(int axis, int n, int* t) {
+AxisKernel pick_axis(int axis, int n, int vk, int* t) {
     switch (axis) {
-        case AX_X1: return pick<S, AX_X1, NST>(n, t);
-        case AX_Y1: return pick<S, AX_Y1, NST>(n, t);
-        case AX_X2: return pick<S, AX_X2, NST>(n, t);
-        case AX_Y2: return pick<S, AX_Y2, NST>(n, t);
+        case AX_X1: return pick<S, AX_X1, NST, 0>(n, t);
+        case AX_X2: return pick<S, AX_X2, NST, 0>(n, t);
+        case AX_Y1: return vk == 2 ? pick<S, AX_Y1, NST, 2>(n, t) : pick<S, AX_Y1, NST, 1>(n, t);
+        case AX_Y2: return vk == 2 ? pick<S, AX_Y2, NST, 2>(n, t) : pick<S, AX_Y2, NST, 1>(n, t);
         default: *t = 0; return nullptr;
     }
 }

@@ -183,6 +183,8 @@ struct hom4d {
     bool have_v = false;
     double norm_tol = 1e-6;
     int pass_plan = 0;           // 0: fused plane pass where built, 1: per-axis passes only
+    int plane_grid = 0;          // grid of the plane pass (0: not built for this size)
+    bool plane_persist = false;  // persistent plane kernel with next-plane prefetch (HOM4D_PLANE_PERSIST=1)
     // gradient recording
     bool rec = false;
     int ckpt_every = 0;
@@ -354,11 +356,11 @@ int run_plane(hom4d* h, KTab kt) {
     a.soft2 = c.soft_nm * c.soft_nm;
     a.ck = c.coulomb_c * h->u.kc;
     a.inv_screen = c.screen_nm > 0.0 ? 1.0 / c.screen_nm : 0.0;
-    HIP_TRY(launch_plane(c.nx, c.ny, h->mixed, a, h->stream));
+    HIP_TRY(launch_plane(c.nx, c.ny, h->mixed, h->plane_persist, h->plane_grid, a, h->stream));
     return sync_check(h, "plane pass");
 }
 
-bool use_plane(const hom4d* h) { return h->pass_plan == 0 && plane_available(h->cfg.nx, h->cfg.ny, h->mixed); }
+bool use_plane(const hom4d* h) { return h->pass_plan == 0 && h->plane_grid > 0; }
 
 // n whole forward steps in three passes per step:
 //   X1 | [X2, V, Y2] (plane) | [Y1, V]  ...  closing X1, X2 halves.
@@ -551,6 +553,14 @@ int hom4d_create(const hom4d_cfg* cfg, void* hip_stream, hom4d** out) {
         return cleanup(HOM4D_EHIP);
     }
     if ((rc = build_twiddles(h)) || (rc = build_kinetic(h)) || (rc = build_coulomb(h))) return cleanup(rc);
+    {
+        const char* e = std::getenv("HOM4D_PLANE_PERSIST");
+        h->plane_persist = e && e[0] == '1';
+    }
+    h->plane_grid = plane_available(nx, ny, h->mixed)
+                        ? plane_grid(nx, ny, h->mixed, h->plane_persist,
+                                     cfg->coulomb_mode == HOM4D_COULOMB_DIRECT ? 2 : 1)
+                        : 0;
     *out = h;
     return HOM4D_OK;
 }

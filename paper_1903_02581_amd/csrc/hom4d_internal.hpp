@@ -62,8 +62,11 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
 // Fused (x2, y2)-plane pass: X2(ktab) -> potential factor -> Y2(ktab2), one
 // workgroup per electron-1 position.  Returns hipErrorInvalidValue when no
 // kernel is built for (nx, ny, storage); plane_available() says beforehand.
+// The kernel is persistent: grid workgroups stride over the nx*ny planes;
+// plane_grid() is the number that fills the device (resident blocks per CU x CUs).
 bool plane_available(int nx, int ny, bool mixed);
-hipError_t launch_plane(int nx, int ny, bool mixed, const PassArgs& a, hipStream_t s);
+int plane_grid(int nx, int ny, bool mixed, bool persist, int vk);
+hipError_t launch_plane(int nx, int ny, bool mixed, bool persist, int grid, const PassArgs& a, hipStream_t s);
 
 // Reductions and elementwise kernels.
 hipError_t launch_init_norm(const double2* pa, const double2* pb, int sym, int nxy, double* part,

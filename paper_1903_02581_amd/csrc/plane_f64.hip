@@ -9,26 +9,22 @@ using dev::plane_threads;
 using dev::Shape;
 
 template <int NX, int NY>
-AxisKernel mk(int* nt) {
+AxisKernel mk(int* nt, bool persist, int vk) {
     constexpr int T = plane_threads(NX, NY, Shape<NX>::t, Shape<NY>::t);
     *nt = T;
-    return k_plane2<double2, NX, NY, T>;
+    if (vk == 2) return persist ? k_plane2<double2, NX, NY, T, true, 2> : k_plane2<double2, NX, NY, T, false, 2>;
+    return persist ? k_plane2<double2, NX, NY, T, true, 1> : k_plane2<double2, NX, NY, T, false, 1>;
 }
 }  // namespace
 
-AxisKernel pick_plane_f64(int nx, int ny, int* nt) {
+AxisKernel pick_plane_f64(int nx, int ny, bool persist, int vk, int* nt) {
 #define HOM4D_PLANE(X, Y) \
-    if (nx == X && ny == Y) return mk<X, Y>(nt);
+    if (nx == X && ny == Y) return mk<X, Y>(nt, persist, vk);
     HOM4D_PLANE(16, 16)
     HOM4D_PLANE(24, 24)
     HOM4D_PLANE(32, 32)
     HOM4D_PLANE(48, 48)
     HOM4D_PLANE(64, 64)
-    HOM4D_PLANE(96, 64)
-    HOM4D_PLANE(64, 96)
-    HOM4D_PLANE(96, 96)
-    HOM4D_PLANE(128, 64)
-    HOM4D_PLANE(64, 128)
     HOM4D_PLANE(48, 16)
     HOM4D_PLANE(16, 48)
 #undef HOM4D_PLANE

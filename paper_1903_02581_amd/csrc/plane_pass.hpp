@@ -31,186 +31,222 @@ template <> struct Shape<64> { static constexpr int n1 = 8, n2 = 8, t = 8; };
 template <> struct Shape<96> { static constexpr int n1 = 12, n2 = 8, t = 4; };
 template <> struct Shape<128> { static constexpr int n1 = 16, n2 = 8, t = 8; };
 
-template <class S, int NX, int NY, int NT>
+// LDS row layout of the plane: element p of row r at r * PLANE_LDP + p + p / 8.
+// The skew of one slot per 8 elements keeps both the row-wise (stride-1 across
+// lanes) and the sub-row (stride-8 within a thread) accesses of the y stage
+// free of bank conflicts; columns (the x stage) are stride-1 across lanes.
+template <int NY>
+struct PlaneLds {
+    static constexpr int row = NY + (NY + 7) / 8;
+    __device__ static __forceinline__ int at(int r, int p) { return r * row + p + (p >> 3); }
+};
+
+// Index offset the compiler cannot see through: added to table indices inside
+// the persistent loop so that table loads are not hoisted out of the loop
+// (hoisting them keeps dozens of values live and spills registers).
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
+// PERSIST = true: workgroup b handles planes r1 = b, b + gridDim.x, ...; the
+// HBM loads of the next plane are issued as soon as the current plane's first
+// transform stage has been written to LDS, so they are in flight while the
+// rest of the current plane is transformed and stored.  PERSIST = false: one
+// plane per workgroup, grid = nx * ny.
+template <class S, int NX, int NY, int NT, bool PERSIST, int VK>
 __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     using SX_ = Shape<NX>;
     using SY_ = Shape<NY>;
+    using LY = PlaneLds<NY>;
     constexpr int A1 = SX_::n1, A2 = SX_::n2, TX = SX_::t;
     constexpr int B1 = SY_::n1, B2 = SY_::n2, TY = SY_::t;
     constexpr int EX = NX / TX, EY = NY / TY;
     constexpr int JAX = A2 / TX, IBX = A1 / TX;
     constexpr int JAY = B2 / TY, IBY = B1 / TY;
-    constexpr int LDP = NY + 1;                   // padded row of the plane in LDS
     constexpr int SLX = NY * TX, QX = (SLX + NT - 1) / NT;
     constexpr int SLY = NX * TY, QY = (SLY + NT - 1) / NT;
-    __shared__ double2 L[NX * LDP];
+    __shared__ double2 L[NX * LY::row];
 
     const int tid = threadIdx.x;
-    const int r1 = blockIdx.x;
-    const int i1 = r1 / NY, j1 = r1 % NY;
-    S* base = reinterpret_cast<S*>(a.psi) + (int64_t)r1 * (NX * NY);
+    const int nplanes = NX * NY;
+    int r1 = blockIdx.x;
+    if (r1 >= nplanes) return;  // whole workgroup leaves together
 
-    // ------------------------------------------------ X2 stage: lines along x2, one per y2
+    // X2 stage slot of this thread: column c (= y2) and thread-in-line t
+    auto slot_x = [&](int q, int* c, int* t) {
+        const int s = tid + NT * q;
+        *c = s % NY;
+        *t = s / NY;
+        return s < SLX;
+    };
+    auto load_plane = [&](int plane, double2 (&vx)[QX][EX]) {
+        const S* base = reinterpret_cast<const S*>(a.psi) + (int64_t)plane * (NX * NY);
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            int c, t;
+            if (slot_x(q, &c, &t)) {
+#pragma unroll
+                for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                    for (int n1 = 0; n1 < A1; ++n1) vx[q][jj * A1 + n1] = ld<S>(base + (n1 * A2 + t + TX * jj) * NY + c);
+            }
+        }
+    };
+
     double2 vx[QX][EX];
-#pragma unroll
-    for (int q = 0; q < QX; ++q) {
-        const int s = tid + NT * q;
-        if (s < SLX) {
-            const int c = s % NY, t = s / NY;
-#pragma unroll
-            for (int jj = 0; jj < JAX; ++jj)
-#pragma unroll
-                for (int n1 = 0; n1 < A1; ++n1) vx[q][jj * A1 + n1] = ld<S>(base + (n1 * A2 + t + TX * jj) * NY + c);
-#pragma unroll
-            for (int jj = 0; jj < JAX; ++jj) {
-                dft<A1, -1>(&vx[q][jj * A1]);
-                if constexpr (A2 > 1) {
-                    const int jc = t + TX * jj;
-#pragma unroll
-                    for (int k1 = 1; k1 < A1; ++k1) vx[q][jj * A1 + k1] = cmul(vx[q][jj * A1 + k1], a.tw[(jc * k1) % NX]);
-                }
-            }
-        }
-    }
-    if constexpr (A2 > 1) {
-#pragma unroll
-        for (int q = 0; q < QX; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLX) {
-                const int c = s % NY, t = s / NY;
-#pragma unroll
-                for (int jj = 0; jj < JAX; ++jj)
-#pragma unroll
-                    for (int k1 = 0; k1 < A1; ++k1) L[(k1 * A2 + t + TX * jj) * LDP + c] = vx[q][jj * A1 + k1];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < QX; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLX) {
-                const int c = s % NY, t = s / NY;
-#pragma unroll
-                for (int ii = 0; ii < IBX; ++ii)
-#pragma unroll
-                    for (int j = 0; j < A2; ++j) vx[q][ii * A2 + j] = L[((t + TX * ii) * A2 + j) * LDP + c];
-#pragma unroll
-                for (int ii = 0; ii < IBX; ++ii) dft<A2, -1>(&vx[q][ii * A2]);
-            }
-        }
-    }
-    // kinetic x phase at (k_x2, y2)
-#pragma unroll
-    for (int q = 0; q < QX; ++q) {
-        const int s = tid + NT * q;
-        if (s < SLX) {
-            const int c = s % NY, t = s / NY;
-            const double2* kt = a.ktab + (int64_t)c * NX;
-#pragma unroll
-            for (int ii = 0; ii < IBX; ++ii)
-#pragma unroll
-                for (int k2 = 0; k2 < A2; ++k2) {
-                    double2 f = kt[t + TX * ii + A1 * k2];
-                    if (a.kconj) f = conjd(f);
-                    vx[q][ii * A2 + k2] = cmul(vx[q][ii * A2 + k2], f);
-                }
-        }
-    }
-    if constexpr (A2 > 1) {
-#pragma unroll
-        for (int q = 0; q < QX; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLX)
-#pragma unroll
-                for (int ii = 0; ii < IBX; ++ii) dft<A2, 1>(&vx[q][ii * A2]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < QX; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLX) {
-                const int c = s % NY, t = s / NY;
-#pragma unroll
-                for (int ii = 0; ii < IBX; ++ii)
-#pragma unroll
-                    for (int j = 0; j < A2; ++j) L[((t + TX * ii) * A2 + j) * LDP + c] = vx[q][ii * A2 + j];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < QX; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLX) {
-                const int c = s % NY, t = s / NY;
-#pragma unroll
-                for (int jj = 0; jj < JAX; ++jj)
-#pragma unroll
-                    for (int k1 = 0; k1 < A1; ++k1) vx[q][jj * A1 + k1] = L[(k1 * A2 + t + TX * jj) * LDP + c];
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < QX; ++q) {
-        const int s = tid + NT * q;
-        if (s < SLX) {
-            const int c = s % NY, t = s / NY;
-#pragma unroll
-            for (int jj = 0; jj < JAX; ++jj) {
-                if constexpr (A2 > 1) {
-                    const int jc = t + TX * jj;
-#pragma unroll
-                    for (int k1 = 1; k1 < A1; ++k1) vx[q][jj * A1 + k1] = cmulc(vx[q][jj * A1 + k1], a.tw[(jc * k1) % NX]);
-                }
-                dft<A1, 1>(&vx[q][jj * A1]);
-            }
-            // potential factor, real space (x2 = n1 * A2 + jc, y2 = c)
-#pragma unroll
-            for (int jj = 0; jj < JAX; ++jj)
-#pragma unroll
-                for (int n1 = 0; n1 < A1; ++n1) {
-                    const double2 f = vfactor(a, i1, j1, n1 * A2 + t + TX * jj, c);
-                    vx[q][jj * A1 + n1] = cmul(vx[q][jj * A1 + n1], f);
-                }
-        }
-    }
-    __syncthreads();  // every X2-stage read of L is done
-#pragma unroll
-    for (int q = 0; q < QX; ++q) {
-        const int s = tid + NT * q;
-        if (s < SLX) {
-            const int c = s % NY, t = s / NY;
-#pragma unroll
-            for (int jj = 0; jj < JAX; ++jj)
-#pragma unroll
-                for (int n1 = 0; n1 < A1; ++n1) L[(n1 * A2 + t + TX * jj) * LDP + c] = vx[q][jj * A1 + n1];
-        }
-    }
-    __syncthreads();
+    load_plane(r1, vx);
 
-    // ------------------------------------------------ Y2 stage: lines along y2, one per x2
-    double2 vy[QY][EY];
+#pragma clang loop unroll(disable)
+    for (; r1 < nplanes; r1 += gridDim.x) {
+        const int i1 = r1 / NY, j1 = r1 % NY;
+        S* base = reinterpret_cast<S*>(a.psi) + (int64_t)r1 * (NX * NY);
+        const int r_next = PERSIST ? r1 + (int)gridDim.x : nplanes;
+        const int z = PERSIST ? opaque_zero() : 0;
+        const double2* twx = a.tw + z;
+        const double2* twy = a.tw2 + z;
+        const double2* kx = a.ktab + z;
+        const double2* ky = a.ktab2 + z;
+        PassArgs av = a;  // potential tables behind the same opaque offset
+        av.a1 = a.a1 + z;
+        av.ac = a.ac ? a.ac + z : nullptr;
+        av.vtab = a.vtab + z;
+
+        // ---------------- X2 stage A: DFT_A1 on the loaded columns, twiddles
 #pragma unroll
-    for (int q = 0; q < QY; ++q) {
-        const int s = tid + NT * q;
-        if (s < SLY) {
-            const int t = s % TY, row = s / TY;
+        for (int q = 0; q < QX; ++q) {
+            int c, t;
+            if (slot_x(q, &c, &t)) {
 #pragma unroll
-            for (int jj = 0; jj < JAY; ++jj)
+                for (int jj = 0; jj < JAX; ++jj) {
+                    dft<A1, -1>(&vx[q][jj * A1]);
+                    if constexpr (A2 > 1) {
+                        const int jc = t + TX * jj;
 #pragma unroll
-                for (int n1 = 0; n1 < B1; ++n1) vy[q][jj * B1 + n1] = L[row * LDP + n1 * B2 + t + TY * jj];
-#pragma unroll
-            for (int jj = 0; jj < JAY; ++jj) {
-                dft<B1, -1>(&vy[q][jj * B1]);
-                if constexpr (B2 > 1) {
-                    const int jc = t + TY * jj;
-#pragma unroll
-                    for (int k1 = 1; k1 < B1; ++k1) vy[q][jj * B1 + k1] = cmul(vy[q][jj * B1 + k1], a.tw2[(jc * k1) % NY]);
+                        for (int k1 = 1; k1 < A1; ++k1)
+                            vx[q][jj * A1 + k1] = cmul(vx[q][jj * A1 + k1], twx[(jc * k1) % NX]);
+                    }
                 }
             }
         }
-    }
-    if constexpr (B2 > 1) {
+        double2 vb[QX][EX];  // stage-B / real-space values of the X2 stage
+        if constexpr (A2 > 1) {
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                int c, t;
+                if (slot_x(q, &c, &t)) {
+#pragma unroll
+                    for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                        for (int k1 = 0; k1 < A1; ++k1) L[LY::at(k1 * A2 + t + TX * jj, c)] = vx[q][jj * A1 + k1];
+                }
+            }
+            // the loaded registers are free: start fetching the next plane
+            if (r_next < nplanes) load_plane(r_next, vx);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                int c, t;
+                if (slot_x(q, &c, &t)) {
+#pragma unroll
+                    for (int ii = 0; ii < IBX; ++ii)
+#pragma unroll
+                        for (int j = 0; j < A2; ++j) vb[q][ii * A2 + j] = L[LY::at((t + TX * ii) * A2 + j, c)];
+#pragma unroll
+                    for (int ii = 0; ii < IBX; ++ii) dft<A2, -1>(&vb[q][ii * A2]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < QX; ++q)
+#pragma unroll
+                for (int e = 0; e < EX; ++e) vb[q][e] = vx[q][e];
+            if (r_next < nplanes) load_plane(r_next, vx);
+        }
+        // kinetic x phase at (k_x2, y2), then the inverse transform
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            int c, t;
+            if (slot_x(q, &c, &t)) {
+                const double2* kt = kx + (int64_t)c * NX;
+#pragma unroll
+                for (int ii = 0; ii < IBX; ++ii)
+#pragma unroll
+                    for (int k2 = 0; k2 < A2; ++k2) {
+                        double2 f = kt[t + TX * ii + A1 * k2];
+                        if (a.kconj) f = conjd(f);
+                        vb[q][ii * A2 + k2] = cmul(vb[q][ii * A2 + k2], f);
+                    }
+                if constexpr (A2 > 1) {
+#pragma unroll
+                    for (int ii = 0; ii < IBX; ++ii) dft<A2, 1>(&vb[q][ii * A2]);
+                }
+            }
+        }
+        if constexpr (A2 > 1) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                int c, t;
+                if (slot_x(q, &c, &t)) {
+#pragma unroll
+                    for (int ii = 0; ii < IBX; ++ii)
+#pragma unroll
+                        for (int j = 0; j < A2; ++j) L[LY::at((t + TX * ii) * A2 + j, c)] = vb[q][ii * A2 + j];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QX; ++q) {
+                int c, t;
+                if (slot_x(q, &c, &t)) {
+#pragma unroll
+                    for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                        for (int k1 = 0; k1 < A1; ++k1) vb[q][jj * A1 + k1] = L[LY::at(k1 * A2 + t + TX * jj, c)];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            int c, t;
+            if (slot_x(q, &c, &t)) {
+#pragma unroll
+                for (int jj = 0; jj < JAX; ++jj) {
+                    if constexpr (A2 > 1) {
+                        const int jc = t + TX * jj;
+#pragma unroll
+                        for (int k1 = 1; k1 < A1; ++k1)
+                            vb[q][jj * A1 + k1] = cmulc(vb[q][jj * A1 + k1], twx[(jc * k1) % NX]);
+                    }
+                    dft<A1, 1>(&vb[q][jj * A1]);
+                }
+                // potential factor in real space at (x2 = n1 * A2 + t + TX * jj, y2 = c)
+#pragma unroll
+                for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                    for (int n1 = 0; n1 < A1; ++n1) {
+                        const double2 f = vfactor<VK>(av, i1, j1, n1 * A2 + t + TX * jj, c);
+                        vb[q][jj * A1 + n1] = cmul(vb[q][jj * A1 + n1], f);
+                    }
+            }
+        }
+        __syncthreads();  // every X2-stage read of L is done
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            int c, t;
+            if (slot_x(q, &c, &t)) {
+#pragma unroll
+                for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                    for (int n1 = 0; n1 < A1; ++n1) L[LY::at(n1 * A2 + t + TX * jj, c)] = vb[q][jj * A1 + n1];
+            }
+        }
         __syncthreads();
+
+        // ---------------- Y2 stage: lines along y2, one per x2 (row of the plane)
+        double2 vy[QY][EY];
 #pragma unroll
         for (int q = 0; q < QY; ++q) {
             const int s = tid + NT * q;
@@ -219,99 +255,123 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                 for (int jj = 0; jj < JAY; ++jj)
 #pragma unroll
-                    for (int k1 = 0; k1 < B1; ++k1) L[row * LDP + k1 * B2 + t + TY * jj] = vy[q][jj * B1 + k1];
-            }
-        }
-        __syncthreads();
+                    for (int n1 = 0; n1 < B1; ++n1) vy[q][jj * B1 + n1] = L[LY::at(row, n1 * B2 + t + TY * jj)];
 #pragma unroll
-        for (int q = 0; q < QY; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLY) {
-                const int t = s % TY, row = s / TY;
+                for (int jj = 0; jj < JAY; ++jj) {
+                    dft<B1, -1>(&vy[q][jj * B1]);
+                    if constexpr (B2 > 1) {
+                        const int jc = t + TY * jj;
 #pragma unroll
-                for (int ii = 0; ii < IBY; ++ii)
-#pragma unroll
-                    for (int j = 0; j < B2; ++j) vy[q][ii * B2 + j] = L[row * LDP + (t + TY * ii) * B2 + j];
-#pragma unroll
-                for (int ii = 0; ii < IBY; ++ii) dft<B2, -1>(&vy[q][ii * B2]);
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < QY; ++q) {
-        const int s = tid + NT * q;
-        if (s < SLY) {
-            const int t = s % TY;
-#pragma unroll
-            for (int ii = 0; ii < IBY; ++ii)
-#pragma unroll
-                for (int k2 = 0; k2 < B2; ++k2) {
-                    double2 f = a.ktab2[t + TY * ii + B1 * k2];
-                    if (a.kconj) f = conjd(f);
-                    vy[q][ii * B2 + k2] = cmul(vy[q][ii * B2 + k2], f);
+                        for (int k1 = 1; k1 < B1; ++k1)
+                            vy[q][jj * B1 + k1] = cmul(vy[q][jj * B1 + k1], twy[(jc * k1) % NY]);
+                    }
                 }
+            }
         }
-    }
-    if constexpr (B2 > 1) {
+        if constexpr (B2 > 1) {
+            __syncthreads();
 #pragma unroll
-        for (int q = 0; q < QY; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLY)
+            for (int q = 0; q < QY; ++q) {
+                const int s = tid + NT * q;
+                if (s < SLY) {
+                    const int t = s % TY, row = s / TY;
 #pragma unroll
-                for (int ii = 0; ii < IBY; ++ii) dft<B2, 1>(&vy[q][ii * B2]);
+                    for (int jj = 0; jj < JAY; ++jj)
+#pragma unroll
+                        for (int k1 = 0; k1 < B1; ++k1) L[LY::at(row, k1 * B2 + t + TY * jj)] = vy[q][jj * B1 + k1];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QY; ++q) {
+                const int s = tid + NT * q;
+                if (s < SLY) {
+                    const int t = s % TY, row = s / TY;
+#pragma unroll
+                    for (int ii = 0; ii < IBY; ++ii)
+#pragma unroll
+                        for (int j = 0; j < B2; ++j) vy[q][ii * B2 + j] = L[LY::at(row, (t + TY * ii) * B2 + j)];
+#pragma unroll
+                    for (int ii = 0; ii < IBY; ++ii) dft<B2, -1>(&vy[q][ii * B2]);
+                }
+            }
         }
-        __syncthreads();
 #pragma unroll
         for (int q = 0; q < QY; ++q) {
             const int s = tid + NT * q;
             if (s < SLY) {
-                const int t = s % TY, row = s / TY;
+                const int t = s % TY;
 #pragma unroll
                 for (int ii = 0; ii < IBY; ++ii)
 #pragma unroll
-                    for (int j = 0; j < B2; ++j) L[row * LDP + (t + TY * ii) * B2 + j] = vy[q][ii * B2 + j];
+                    for (int k2 = 0; k2 < B2; ++k2) {
+                        double2 f = ky[t + TY * ii + B1 * k2];
+                        if (a.kconj) f = conjd(f);
+                        vy[q][ii * B2 + k2] = cmul(vy[q][ii * B2 + k2], f);
+                    }
+                if constexpr (B2 > 1) {
+#pragma unroll
+                    for (int ii = 0; ii < IBY; ++ii) dft<B2, 1>(&vy[q][ii * B2]);
+                }
             }
         }
-        __syncthreads();
+        if constexpr (B2 > 1) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QY; ++q) {
+                const int s = tid + NT * q;
+                if (s < SLY) {
+                    const int t = s % TY, row = s / TY;
+#pragma unroll
+                    for (int ii = 0; ii < IBY; ++ii)
+#pragma unroll
+                        for (int j = 0; j < B2; ++j) L[LY::at(row, (t + TY * ii) * B2 + j)] = vy[q][ii * B2 + j];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QY; ++q) {
+                const int s = tid + NT * q;
+                if (s < SLY) {
+                    const int t = s % TY, row = s / TY;
+#pragma unroll
+                    for (int jj = 0; jj < JAY; ++jj)
+#pragma unroll
+                        for (int k1 = 0; k1 < B1; ++k1) vy[q][jj * B1 + k1] = L[LY::at(row, k1 * B2 + t + TY * jj)];
+                }
+            }
+        }
 #pragma unroll
         for (int q = 0; q < QY; ++q) {
             const int s = tid + NT * q;
             if (s < SLY) {
                 const int t = s % TY, row = s / TY;
+#pragma unroll
+                for (int jj = 0; jj < JAY; ++jj) {
+                    if constexpr (B2 > 1) {
+                        const int jc = t + TY * jj;
+#pragma unroll
+                        for (int k1 = 1; k1 < B1; ++k1)
+                            vy[q][jj * B1 + k1] = cmulc(vy[q][jj * B1 + k1], twy[(jc * k1) % NY]);
+                    }
+                    dft<B1, 1>(&vy[q][jj * B1]);
+                }
 #pragma unroll
                 for (int jj = 0; jj < JAY; ++jj)
 #pragma unroll
-                    for (int k1 = 0; k1 < B1; ++k1) vy[q][jj * B1 + k1] = L[row * LDP + k1 * B2 + t + TY * jj];
+                    for (int n1 = 0; n1 < B1; ++n1) st<S>(base + row * NY + n1 * B2 + t + TY * jj, vy[q][jj * B1 + n1]);
             }
         }
-    }
-#pragma unroll
-    for (int q = 0; q < QY; ++q) {
-        const int s = tid + NT * q;
-        if (s < SLY) {
-            const int t = s % TY, row = s / TY;
-#pragma unroll
-            for (int jj = 0; jj < JAY; ++jj) {
-                if constexpr (B2 > 1) {
-                    const int jc = t + TY * jj;
-#pragma unroll
-                    for (int k1 = 1; k1 < B1; ++k1) vy[q][jj * B1 + k1] = cmulc(vy[q][jj * B1 + k1], a.tw2[(jc * k1) % NY]);
-                }
-                dft<B1, 1>(&vy[q][jj * B1]);
-            }
-#pragma unroll
-            for (int jj = 0; jj < JAY; ++jj)
-#pragma unroll
-                for (int n1 = 0; n1 < B1; ++n1) st<S>(base + row * NY + n1 * B2 + t + TY * jj, vy[q][jj * B1 + n1]);
-        }
+        if constexpr (!PERSIST) break;
+        __syncthreads();  // the next plane reuses L
     }
 }
 
-// Threads per plane workgroup: enough for the larger of the two stages, at most 256.
+// Threads per plane workgroup: enough for the larger of the two stages, at most 512.
 constexpr int plane_threads(int nx, int ny, int tx, int ty) {
     const int s = (ny * tx > nx * ty) ? ny * tx : nx * ty;
     const int r = ((s + 63) / 64) * 64;
-    return r > 256 ? 256 : r;
+    return r > 512 ? 512 : r;
 }
 
 }  // namespace dev
