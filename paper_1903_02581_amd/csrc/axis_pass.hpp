@@ -166,6 +166,22 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         sN = 1;
     }
 
+    // twiddles (and, on y axes, the kinetic factor) staged in LDS after the exchange area
+    constexpr bool KT_LDS = (AXIS == AX_Y1 || AXIS == AX_Y2);
+    double2* TWL = lds + (N2 > 1 ? NST * N * (W + 1) : 0);
+    for (int i = tid; i < (KT_LDS ? 2 * N : N); i += T * W) {
+        double2 v;
+        if (i < N) {
+            v = a.tw[i];
+        } else {
+            v = a.ktab[i - N];
+            if (a.kconj) v = conjd(v);
+        }
+        TWL[i] = v;
+    }
+    __syncthreads();
+    const double2* twl = TWL;
+
     S* ps[NST];
     ps[0] = reinterpret_cast<S*>(a.psi) + base;
     if constexpr (NST == 2) ps[1] = reinterpret_cast<S*>(a.lam) + base;
@@ -214,7 +230,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
             if constexpr (N2 > 1) {
                 const int jc = t + T * jj;
 #pragma unroll
-                for (int k1 = 1; k1 < N1; ++k1) v[s][jj * N1 + k1] = cmul(v[s][jj * N1 + k1], a.tw[(jc * k1) % N]);
+                for (int k1 = 1; k1 < N1; ++k1) v[s][jj * N1 + k1] = cmul(v[s][jj * N1 + k1], twl[(jc * k1) % N]);
             }
         }
     }
@@ -265,8 +281,13 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
             const int k = t + T * ii + N1 * k2;
-            double2 f = kt[k];
-            if (a.kconj) f = conjd(f);
+            double2 f;
+            if constexpr (KT_LDS) {
+                f = twl[N + k];
+            } else {
+                f = kt[k];
+                if (a.kconj) f = conjd(f);
+            }
 #pragma unroll
             for (int s = 0; s < NST; ++s) v[s][ii * N2 + k2] = cmul(v[s][ii * N2 + k2], f);
         }
@@ -300,7 +321,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
             if constexpr (N2 > 1) {
                 const int jc = t + T * jj;
 #pragma unroll
-                for (int k1 = 1; k1 < N1; ++k1) v[s][jj * N1 + k1] = cmulc(v[s][jj * N1 + k1], a.tw[(jc * k1) % N]);
+                for (int k1 = 1; k1 < N1; ++k1) v[s][jj * N1 + k1] = cmulc(v[s][jj * N1 + k1], twl[(jc * k1) % N]);
             }
             dft<N1, 1>(&v[s][jj * N1]);
         }

@@ -128,7 +128,7 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad) {
     p.nlines = nxy * nxy / p.n;
     int64_t w = 256 / sh.t;
     if (sh.n2 > 1) {
-        const int64_t cap = 65536 / ((int64_t)nst * p.n * 16) - 1;
+        const int64_t cap = (65536 - 2 * p.n * 16) / ((int64_t)nst * p.n * 16) - 1;
         while (w > cap) w >>= 1;
     }
     w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
@@ -136,9 +136,11 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad) {
     if (axis == AX_Y2 && grad) w = std::min<int64_t>(w, ilog2_pow2_divisor(nx));
     if (w < 1) w = 1;
     p.W = (int)w;
-    size_t ex = sh.n2 > 1 ? (size_t)nst * p.n * (p.W + 1) * sizeof(double2) : 0;
-    size_t red = nst == 2 ? (size_t)sh.t * p.W * sizeof(double) : 0;
-    p.lds = std::max(ex, red);
+    // exchange area, then the staged twiddles / kinetic factor (2n entries); the
+    // dual-state reduction scratch reuses the start of the allocation at the end
+    const size_t ex = sh.n2 > 1 ? (size_t)nst * p.n * (p.W + 1) * sizeof(double2) : 0;
+    const size_t red = nst == 2 ? (size_t)sh.t * p.W * sizeof(double) : 0;
+    p.lds = std::max(ex + (size_t)2 * p.n * sizeof(double2), red);
     return p;
 }
 

@@ -68,11 +68,23 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     constexpr int SLX = NY * TX, QX = (SLX + NT - 1) / NT;
     constexpr int SLY = NX * TY, QY = (SLY + NT - 1) / NT;
     __shared__ double2 L[NX * LY::row];
+    __shared__ double2 TW[NX + 2 * NY];  // x twiddles, y twiddles, y kinetic factor
 
     const int tid = threadIdx.x;
     const int nplanes = NX * NY;
     int r1 = blockIdx.x;
     if (r1 >= nplanes) return;  // whole workgroup leaves together
+    for (int i = tid; i < NX + 2 * NY; i += NT) {
+        double2 v;
+        if (i < NX) v = a.tw[i];
+        else if (i < NX + NY) v = a.tw2[i - NX];
+        else {
+            v = a.ktab2[i - NX - NY];
+            if (a.kconj) v = conjd(v);
+        }
+        TW[i] = v;
+    }
+    __syncthreads();
 
     // X2 stage slot of this thread: column c (= y2) and thread-in-line t
     auto slot_x = [&](int q, int* c, int* t) {
@@ -104,10 +116,10 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
         S* base = reinterpret_cast<S*>(a.psi) + (int64_t)r1 * (NX * NY);
         const int r_next = PERSIST ? r1 + (int)gridDim.x : nplanes;
         const int z = PERSIST ? opaque_zero() : 0;
-        const double2* twx = a.tw + z;
-        const double2* twy = a.tw2 + z;
+        const double2* twx = TW;
+        const double2* twy = TW + NX;
+        const double2* ky = TW + NX + NY;
         const double2* kx = a.ktab + z;
-        const double2* ky = a.ktab2 + z;
         PassArgs av = a;  // potential tables behind the same opaque offset
         av.a1 = a.a1 + z;
         av.ac = a.ac ? a.ac + z : nullptr;
@@ -305,9 +317,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                 for (int ii = 0; ii < IBY; ++ii)
 #pragma unroll
                     for (int k2 = 0; k2 < B2; ++k2) {
-                        double2 f = ky[t + TY * ii + B1 * k2];
-                        if (a.kconj) f = conjd(f);
-                        vy[q][ii * B2 + k2] = cmul(vy[q][ii * B2 + k2], f);
+                        vy[q][ii * B2 + k2] = cmul(vy[q][ii * B2 + k2], ky[t + TY * ii + B1 * k2]);
                     }
                 if constexpr (B2 > 1) {
 #pragma unroll
