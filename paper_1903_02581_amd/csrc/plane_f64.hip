@@ -1,4 +1,6 @@
 // Instantiations of the fused (x2, y2)-plane pass for double2 storage.
+#include <cstdlib>
+
 #include "plane_pass.hpp"
 
 namespace hom4d_impl {
@@ -7,6 +9,11 @@ using dev::AxisKernel;
 using dev::k_plane2;
 using dev::plane_threads;
 using dev::Shape;
+
+bool plane_small_blocks() {
+    const char* e = std::getenv("HOM4D_PLANE_NT");
+    return e && e[0] == '2';
+}
 
 template <int NX, int NY>
 AxisKernel mk(int* nt, bool persist, int vk) {
@@ -18,6 +25,10 @@ AxisKernel mk(int* nt, bool persist, int vk) {
 }  // namespace
 
 AxisKernel pick_plane_f64(int nx, int ny, bool persist, int vk, int* nt) {
+    if (nx == 64 && ny == 64 && !persist && plane_small_blocks()) {
+        *nt = 256;
+        return vk == 2 ? k_plane2<double2, 64, 64, 256, false, 2> : k_plane2<double2, 64, 64, 256, false, 1>;
+    }
 #define HOM4D_PLANE(X, Y) \
     if (nx == X && ny == Y) return mk<X, Y>(nt, persist, vk);
     HOM4D_PLANE(16, 16)

@@ -46,7 +46,7 @@ struct PlaneLds {
 // (hoisting them keeps dozens of values live and spills registers).
 __device__ __forceinline__ int opaque_zero() {
     int z = 0;
-    asm volatile("" : "+v"(z));
+    asm volatile("" : "+s"(z));
     return z;
 }
 
