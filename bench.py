@@ -112,6 +112,55 @@ def cpu_baseline(w, budget_s):
     return n, el
 
 
+def config_throughput(name, precision, steps, plan=None):
+    """Short timed run of another named workload (same kernels, other sizes)."""
+    import torch
+    from workloads import preset
+    w = preset(name)
+    p = make_prop(w, precision)
+    if plan is not None:
+        p.set_pass_plan(plan)
+    p.step(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.step(steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    out = {"workload": name, "nx": w.nx, "ny": w.ny, "points": w.points, "precision": precision,
+           "steps": steps, "passes_per_step": p.passes_per_step,
+           "gp_steps_per_s": w.points * steps / sec, "ms_per_step": sec / steps * 1e3}
+    sbytes = 16 if precision == "fp64" else 8
+    out["effective_GBps"] = out["gp_steps_per_s"] * 2 * sbytes * p.passes_per_step / 1e9
+    out["effective_frac_of_hbm_peak"] = out["effective_GBps"] / HBM_PEAK_GBS
+    p.close()
+    del p
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_throughput(precision):
+    """Forward with checkpoints + reverse sweep on the 48x48, 1000-step gradient workload."""
+    import torch
+    from workloads import preset
+    w = preset("diff")
+    p = make_prop(w, precision)
+    p.set_norm_tol(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.grad_begin(w.ckpt_every, w.steps)
+    p.step(w.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss, dldv, dldb = p.grad_backward(w.w_top)
+    t2 = time.perf_counter()
+    p.close()
+    return {"workload": "diff: 48x48, 1000 steps, checkpoint every 100", "precision": precision,
+            "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "backward_gp_steps_per_s": w.points * w.steps / (t2 - t1),
+            "loss_p_b": loss, "dL_dB": dldb, "sum_dL_dV": float(dldv.sum()),
+            "sum_abs_dL_dV": float(np.abs(dldv).sum())}
+
+
 def read_traffic(nbytes_alg):
     try:
         with open(TRAFFIC_FILE) as f:
@@ -133,6 +182,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads' throughput and the adjoint timing")
     ap.add_argument("--plan", type=int, default=0, choices=[0, 1],
                     help="0: fused three-pass steps (default), 1: four per-axis passes")
     ap.add_argument("--profile-passes", type=int, default=0,
@@ -203,6 +254,20 @@ def main():
             "pass_seconds": passes_m,
         }
 
+    extras = None
+    if not args.no_extras:
+        extras = {
+            "configs": [
+                config_throughput("mixed", "fp64", 100),
+                config_throughput("mixed", "mixed", 200),
+                config_throughput("fp64_128", "fp64", 50),
+                config_throughput("full", "mixed", 50),
+                config_throughput("diff", "fp64", 500),
+                config_throughput("tiny", "fp64", 2000),
+            ],
+            "adjoint": [adjoint_throughput("fp64"), adjoint_throughput("mixed")],
+        }
+
     cpu = None
     if not args.no_cpu:
         n_cpu, t_cpu = cpu_baseline(w, args.cpu_budget)
@@ -237,6 +302,7 @@ def main():
                      "avg_launch_s": passes[dom], "pass_seconds": passes},
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "extras": extras,
     }
     print(json.dumps(line))
 

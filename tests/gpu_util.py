@@ -1,4 +1,5 @@
 """Shared helpers for the GPU parity tests (test infrastructure)."""
+import os
 import sys
 
 import numpy as np
@@ -7,9 +8,15 @@ import oracle as O
 
 
 def announce(msg: str) -> None:
-    """Write straight to the real stderr so the case is named even if the run dies."""
-    sys.__stderr__.write(f"[gpu-test] {msg}\n")
+    """Name the case on the real stderr (flushed, so it survives a dying run) and, when
+    HOM4D_TEST_LOG names a file, append it there too (pytest captures stderr)."""
+    line = f"[gpu-test] {msg}\n"
+    sys.__stderr__.write(line)
     sys.__stderr__.flush()
+    path = os.environ.get("HOM4D_TEST_LOG")
+    if path:
+        with open(path, "a") as f:
+            f.write(line)
 
 
 def grid_of(w, **kw):
