@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads' throughput and the adjoint timing")
+    ap.add_argument("--workload", default="mid",
+                    help="named workload for the timed run (default: the 64x64 case, run 0 of its sweep)")
     ap.add_argument("--plan", type=int, default=0, choices=[0, 1],
                     help="0: fused three-pass steps (default), 1: four per-axis passes")
     ap.add_argument("--profile-passes", type=int, default=0,
@@ -200,7 +202,7 @@ def main():
     global PLAN
     PLAN = args.plan
 
-    w = preset("mid", run=0)
+    w = preset("mid", run=0) if args.workload == "mid" else preset(args.workload)
     P = w.points
     if args.profile_passes:
         prop = make_prop(w, args.precision)

@@ -259,8 +259,12 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     }
 
     // ---- reciprocal space: gradient contribution and the kinetic phase
+    // x kinetic factor table: y-major [y][k] on the x1 pass (all lanes of a block share y1,
+    // each thread's k values are contiguous), k-major [k][y] on the x2 pass (neighbouring
+    // lanes hold neighbouring y2 at the same k)
     const int yrow = (AXIS == AX_X1) ? j1 : ((AXIS == AX_X2) ? j2 : 0);
-    const double2* kt = a.ktab + ((AXIS == AX_X1 || AX_X2 == AXIS) ? (int64_t)yrow * N : 0);
+    const double2* kt = a.ktab + (AXIS == AX_X1 ? (int64_t)yrow * N : (int64_t)yrow);
+    const int64_t kstride = AXIS == AX_X1 ? 1 : a.ny;
     if constexpr (NST == 2 && (AXIS == AX_X1 || AXIS == AX_X2)) {
         if (a.gflags & G_GB) {
             const double yv = a.y0 + a.ystep * yrow;
@@ -285,7 +289,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
             if constexpr (KT_LDS) {
                 f = twl[N + k];
             } else {
-                f = kt[k];
+                f = kt[k * kstride];
                 if (a.kconj) f = conjd(f);
             }
 #pragma unroll

@@ -164,8 +164,10 @@ struct hom4d {
     // device tables (FP64)
     double2* tw_x = nullptr;     // [nx]
     double2* tw_y = nullptr;     // [ny]
-    double2* kx_half = nullptr;  // [ny][nx]  exp(-i theta_x(dt/2)) / nx
-    double2* kx_full = nullptr;  // [ny][nx]  exp(-i theta_x(dt)) / nx
+    double2* kx_half = nullptr;  // [ny][nx] (y-major)  exp(-i theta_x(dt/2)) / nx
+    double2* kx_full = nullptr;  // [ny][nx] (y-major)  exp(-i theta_x(dt)) / nx
+    double2* kxt_half = nullptr; // the same two tables k-major, [nx][ny]
+    double2* kxt_full = nullptr;
     double2* ky_full = nullptr;  // [ny]      exp(-i theta_y(dt)) / ny
     double2* a1_half = nullptr;  // [nx*ny]   exp(-i (dt/2) V / hbar)
     double2* ac_half = nullptr;  // [(2nx-1)(2ny-1)]
@@ -185,8 +187,7 @@ struct hom4d {
     bool have_v = false;
     double norm_tol = 1e-6;
     int pass_plan = 0;           // 0: fused plane pass where built, 1: per-axis passes only
-    int plane_grid = 0;          // grid of the plane pass (0: not built for this size)
-    bool plane_persist = false;  // persistent plane kernel with next-plane prefetch (HOM4D_PLANE_PERSIST=1)
+    bool plane_built = false;    // a fused plane kernel exists for (nx, ny, precision)
     // gradient recording
     bool rec = false;
     int ckpt_every = 0;
@@ -232,7 +233,7 @@ int build_kinetic(hom4d* h) {
     const double eb = h->u.eoh * c.b_tesla;
     for (int which = 0; which < 2; ++which) {
         const double tau = which == 0 ? 0.5 * c.dt_fs : c.dt_fs;
-        std::vector<double2> t((size_t)c.ny * c.nx);
+        std::vector<double2> t((size_t)c.ny * c.nx), tt((size_t)c.ny * c.nx);
         for (int j = 0; j < c.ny; ++j) {
             const double shift = ygrid(c, j) * eb;
             for (int m = 0; m < c.nx; ++m) {
@@ -240,10 +241,13 @@ int build_kinetic(hom4d* h) {
                 const double th = (tau / h->u.hbar) * h->u.kappa * (q * q);
                 double f[2];
                 phase(th, 1.0 / c.nx, f);
-                t[(size_t)j * c.nx + m] = make_double2(f[0], f[1]);
+                t[(size_t)j * c.nx + m] = make_double2(f[0], f[1]);   // y-major
+                tt[(size_t)m * c.ny + j] = make_double2(f[0], f[1]);  // k-major
             }
         }
         int rc = upload(h, which == 0 ? h->kx_half : h->kx_full, t.data(), t.size() * sizeof(double2));
+        if (rc) return rc;
+        rc = upload(h, which == 0 ? h->kxt_half : h->kxt_full, tt.data(), tt.size() * sizeof(double2));
         if (rc) return rc;
     }
     std::vector<double2> ty(c.ny);
@@ -306,7 +310,10 @@ int run_pass(hom4d* h, int axis, KTab kt, int vmode, int nst, void* lam, bool re
     a.W = p.W;
     a.kconj = reverse ? 1 : 0;
     a.tw = (axis == AX_X1 || axis == AX_X2) ? h->tw_x : h->tw_y;
-    a.ktab = kt == KX_HALF ? h->kx_half : (kt == KX_FULL ? h->kx_full : h->ky_full);
+    if (axis == AX_X2)
+        a.ktab = kt == KX_HALF ? h->kxt_half : h->kxt_full;
+    else
+        a.ktab = kt == KX_HALF ? h->kx_half : (kt == KX_FULL ? h->kx_full : h->ky_full);
     a.vmode = vmode;
     a.a1 = h->a1_half;
     a.ac = (c.coulomb_c != 0.0) ? h->ac_half : nullptr;
@@ -345,7 +352,7 @@ int run_plane(hom4d* h, KTab kt) {
     a.nx = c.nx;
     a.ny = c.ny;
     a.tw = h->tw_x;
-    a.ktab = kt == KX_HALF ? h->kx_half : h->kx_full;
+    a.ktab = kt == KX_HALF ? h->kxt_half : h->kxt_full;  // k-major
     a.tw2 = h->tw_y;
     a.ktab2 = h->ky_full;
     a.a1 = h->a1_half;
@@ -358,11 +365,11 @@ int run_plane(hom4d* h, KTab kt) {
     a.soft2 = c.soft_nm * c.soft_nm;
     a.ck = c.coulomb_c * h->u.kc;
     a.inv_screen = c.screen_nm > 0.0 ? 1.0 / c.screen_nm : 0.0;
-    HIP_TRY(launch_plane(c.nx, c.ny, h->mixed, h->plane_persist, h->plane_grid, a, h->stream));
+    HIP_TRY(launch_plane(c.nx, c.ny, h->mixed, a, h->stream));
     return sync_check(h, "plane pass");
 }
 
-bool use_plane(const hom4d* h) { return h->pass_plan == 0 && h->plane_grid > 0; }
+bool use_plane(const hom4d* h) { return h->pass_plan == 0 && h->plane_built; }
 
 // n whole forward steps in three passes per step:
 //   X1 | [X2, V, Y2] (plane) | [Y1, V]  ...  closing X1, X2 halves.
@@ -478,7 +485,7 @@ int gather(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1, const int32_t*
 }
 
 void free_all(hom4d* h) {
-    void* bufs[] = {h->tw_x, h->tw_y, h->kx_half, h->kx_full, h->ky_full, h->a1_half, h->ac_half, h->v_dev,
+    void* bufs[] = {h->tw_x, h->tw_y, h->kx_half, h->kx_full, h->kxt_half, h->kxt_full, h->ky_full, h->a1_half, h->ac_half, h->v_dev,
                     h->w_dev, h->red_part, h->red_out, h->ix_dev, h->slice_dev, h->orb_dev, h->g_buf};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -531,6 +538,8 @@ int hom4d_create(const hom4d_cfg* cfg, void* hip_stream, hom4d** out) {
         {(void**)&h->tw_y, ny * sizeof(double2)},
         {(void**)&h->kx_half, (size_t)nx * ny * sizeof(double2)},
         {(void**)&h->kx_full, (size_t)nx * ny * sizeof(double2)},
+        {(void**)&h->kxt_half, (size_t)nx * ny * sizeof(double2)},
+        {(void**)&h->kxt_full, (size_t)nx * ny * sizeof(double2)},
         {(void**)&h->ky_full, ny * sizeof(double2)},
         {(void**)&h->a1_half, (size_t)nx * ny * sizeof(double2)},
         {(void**)&h->ac_half, (size_t)(2 * nx - 1) * (2 * ny - 1) * sizeof(double2)},
@@ -555,14 +564,7 @@ int hom4d_create(const hom4d_cfg* cfg, void* hip_stream, hom4d** out) {
         return cleanup(HOM4D_EHIP);
     }
     if ((rc = build_twiddles(h)) || (rc = build_kinetic(h)) || (rc = build_coulomb(h))) return cleanup(rc);
-    {
-        const char* e = std::getenv("HOM4D_PLANE_PERSIST");
-        h->plane_persist = e && e[0] == '1';
-    }
-    h->plane_grid = plane_available(nx, ny, h->mixed)
-                        ? plane_grid(nx, ny, h->mixed, h->plane_persist,
-                                     cfg->coulomb_mode == HOM4D_COULOMB_DIRECT ? 2 : 1)
-                        : 0;
+    h->plane_built = plane_available(nx, ny, h->mixed);
     *out = h;
     return HOM4D_OK;
 }

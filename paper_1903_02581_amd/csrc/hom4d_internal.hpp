@@ -26,7 +26,7 @@ struct PassArgs {
     int W;                    // lines per block
     int kconj;                // use conj(ktab) and conj(potential factor): reverse sweep
     const double2* tw;        // twiddles exp(-2 pi i j / n), j < n
-    const double2* ktab;      // k-space factor incl. 1/n: [ny][nx] for x axes, [ny] for y axes
+    const double2* ktab;      // k-space factor incl. 1/n: x1 pass [ny][nx], x2 and plane passes [nx][ny], y [ny]
     const double2* tw2;       // plane pass only: twiddles of the y lines
     const double2* ktab2;     // plane pass only: y kinetic factor [ny]
     int vmode;                // 0: none, 1: potential factor before the transform, 2: after
@@ -62,11 +62,8 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
 // Fused (x2, y2)-plane pass: X2(ktab) -> potential factor -> Y2(ktab2), one
 // workgroup per electron-1 position.  Returns hipErrorInvalidValue when no
 // kernel is built for (nx, ny, storage); plane_available() says beforehand.
-// The kernel is persistent: grid workgroups stride over the nx*ny planes;
-// plane_grid() is the number that fills the device (resident blocks per CU x CUs).
 bool plane_available(int nx, int ny, bool mixed);
-int plane_grid(int nx, int ny, bool mixed, bool persist, int vk);
-hipError_t launch_plane(int nx, int ny, bool mixed, bool persist, int grid, const PassArgs& a, hipStream_t s);
+hipError_t launch_plane(int nx, int ny, bool mixed, const PassArgs& a, hipStream_t s);
 
 // Reductions and elementwise kernels.
 hipError_t launch_init_norm(const double2* pa, const double2* pb, int sym, int nxy, double* part,

@@ -32,8 +32,8 @@ AxisKernel pick_axis_f64_1(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f64_2(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f32_1(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f32_2(int axis, int n, int vk, int* t);
-AxisKernel pick_plane_f64(int nx, int ny, bool persist, int vk, int* nt);
-AxisKernel pick_plane_f32(int nx, int ny, bool persist, int vk, int* nt);
+AxisKernel pick_plane_f64(int nx, int ny, int vk, int* nt);
+AxisKernel pick_plane_f32(int nx, int ny, int vk, int* nt);
 
 namespace {
 
@@ -214,32 +214,15 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
 
 bool plane_available(int nx, int ny, bool mixed) {
     int nt = 0;
-    return (mixed ? pick_plane_f32(nx, ny, true, 1, &nt) : pick_plane_f64(nx, ny, true, 1, &nt)) != nullptr;
+    return (mixed ? pick_plane_f32(nx, ny, 1, &nt) : pick_plane_f64(nx, ny, 1, &nt)) != nullptr;
 }
 
-int plane_grid(int nx, int ny, bool mixed, bool persist, int vk) {
-    int nt = 0;
-    AxisKernel fn = mixed ? pick_plane_f32(nx, ny, persist, vk, &nt) : pick_plane_f64(nx, ny, persist, vk, &nt);
-    if (!fn) return 0;
-    if (!persist) return nx * ny;
-    int dev = 0, cus = 0, per_cu = 0;
-    const int planes = nx * ny;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), nt, 0) !=
-            hipSuccess ||
-        cus <= 0 || per_cu <= 0)
-        return planes;
-    const int64_t g = (int64_t)cus * per_cu;
-    return g < planes ? (int)g : planes;
-}
-
-hipError_t launch_plane(int nx, int ny, bool mixed, bool persist, int grid, const PassArgs& a, hipStream_t s) {
+hipError_t launch_plane(int nx, int ny, bool mixed, const PassArgs& a, hipStream_t s) {
     int nt = 0;
     const int vk = a.vdirect ? 2 : 1;
-    AxisKernel fn = mixed ? pick_plane_f32(nx, ny, persist, vk, &nt) : pick_plane_f64(nx, ny, persist, vk, &nt);
-    if (!fn || nt <= 0 || nt > 512 || grid <= 0 || grid > nx * ny) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(nt), 0, s, a);
+    AxisKernel fn = mixed ? pick_plane_f32(nx, ny, vk, &nt) : pick_plane_f64(nx, ny, vk, &nt);
+    if (!fn || nt <= 0 || nt > 512) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3((unsigned)(nx * ny)), dim3(nt), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,6 +1,4 @@
 // Instantiations of the fused (x2, y2)-plane pass for double2 storage.
-#include <cstdlib>
-
 #include "plane_pass.hpp"
 
 namespace hom4d_impl {
@@ -10,27 +8,19 @@ using dev::k_plane2;
 using dev::plane_threads;
 using dev::Shape;
 
-bool plane_small_blocks() {
-    const char* e = std::getenv("HOM4D_PLANE_NT");
-    return e && e[0] == '2';
-}
-
 template <int NX, int NY>
-AxisKernel mk(int* nt, bool persist, int vk) {
+AxisKernel mk(int* nt, int vk) {
     constexpr int T = plane_threads(NX, NY, Shape<NX>::t, Shape<NY>::t);
     *nt = T;
-    if (vk == 2) return persist ? k_plane2<double2, NX, NY, T, true, 2> : k_plane2<double2, NX, NY, T, false, 2>;
-    return persist ? k_plane2<double2, NX, NY, T, true, 1> : k_plane2<double2, NX, NY, T, false, 1>;
+    return vk == 2 ? k_plane2<double2, NX, NY, T, 2> : k_plane2<double2, NX, NY, T, 1>;
 }
 }  // namespace
 
-AxisKernel pick_plane_f64(int nx, int ny, bool persist, int vk, int* nt) {
-    if (nx == 64 && ny == 64 && !persist && plane_small_blocks()) {
-        *nt = 256;
-        return vk == 2 ? k_plane2<double2, 64, 64, 256, false, 2> : k_plane2<double2, 64, 64, 256, false, 1>;
-    }
+// Plane sizes with a fused kernel: the FP64 LDS image (nx rows of ny + ny/8
+// slots) must fit in 160 KB with room for a second workgroup.
+AxisKernel pick_plane_f64(int nx, int ny, int vk, int* nt) {
 #define HOM4D_PLANE(X, Y) \
-    if (nx == X && ny == Y) return mk<X, Y>(nt, persist, vk);
+    if (nx == X && ny == Y) return mk<X, Y>(nt, vk);
     HOM4D_PLANE(16, 16)
     HOM4D_PLANE(24, 24)
     HOM4D_PLANE(32, 32)

@@ -41,21 +41,8 @@ struct PlaneLds {
     __device__ static __forceinline__ int at(int r, int p) { return r * row + p + (p >> 3); }
 };
 
-// Index offset the compiler cannot see through: added to table indices inside
-// the persistent loop so that table loads are not hoisted out of the loop
-// (hoisting them keeps dozens of values live and spills registers).
-__device__ __forceinline__ int opaque_zero() {
-    int z = 0;
-    asm volatile("" : "+s"(z));
-    return z;
-}
-
-// PERSIST = true: workgroup b handles planes r1 = b, b + gridDim.x, ...; the
-// HBM loads of the next plane are issued as soon as the current plane's first
-// transform stage has been written to LDS, so they are in flight while the
-// rest of the current plane is transformed and stored.  PERSIST = false: one
-// plane per workgroup, grid = nx * ny.
-template <class S, int NX, int NY, int NT, bool PERSIST, int VK>
+// One plane per workgroup, grid = nx * ny.
+template <class S, int NX, int NY, int NT, int VK>
 __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     using SX_ = Shape<NX>;
     using SY_ = Shape<NY>;
@@ -71,9 +58,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     __shared__ double2 TW[NX + 2 * NY];  // x twiddles, y twiddles, y kinetic factor
 
     const int tid = threadIdx.x;
-    const int nplanes = NX * NY;
-    int r1 = blockIdx.x;
-    if (r1 >= nplanes) return;  // whole workgroup leaves together
     for (int i = tid; i < NX + 2 * NY; i += NT) {
         double2 v;
         if (i < NX) v = a.tw[i];
@@ -84,7 +68,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
         }
         TW[i] = v;
     }
-    __syncthreads();
 
     // X2 stage slot of this thread: column c (= y2) and thread-in-line t
     auto slot_x = [&](int q, int* c, int* t) {
@@ -93,37 +76,28 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
         *t = s / NY;
         return s < SLX;
     };
-    auto load_plane = [&](int plane, double2 (&vx)[QX][EX]) {
-        const S* base = reinterpret_cast<const S*>(a.psi) + (int64_t)plane * (NX * NY);
-#pragma unroll
-        for (int q = 0; q < QX; ++q) {
-            int c, t;
-            if (slot_x(q, &c, &t)) {
-#pragma unroll
-                for (int jj = 0; jj < JAX; ++jj)
-#pragma unroll
-                    for (int n1 = 0; n1 < A1; ++n1) vx[q][jj * A1 + n1] = ld<S>(base + (n1 * A2 + t + TX * jj) * NY + c);
-            }
-        }
-    };
 
+    const int r1 = blockIdx.x;
+    const int i1 = r1 / NY, j1 = r1 % NY;
+    S* base = reinterpret_cast<S*>(a.psi) + (int64_t)r1 * (NX * NY);
     double2 vx[QX][EX];
-    load_plane(r1, vx);
-
-#pragma clang loop unroll(disable)
-    for (; r1 < nplanes; r1 += gridDim.x) {
-        const int i1 = r1 / NY, j1 = r1 % NY;
-        S* base = reinterpret_cast<S*>(a.psi) + (int64_t)r1 * (NX * NY);
-        const int r_next = PERSIST ? r1 + (int)gridDim.x : nplanes;
-        const int z = PERSIST ? opaque_zero() : 0;
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+        int c, t;
+        if (slot_x(q, &c, &t)) {
+#pragma unroll
+            for (int jj = 0; jj < JAX; ++jj)
+#pragma unroll
+                for (int n1 = 0; n1 < A1; ++n1) vx[q][jj * A1 + n1] = ld<S>(base + (n1 * A2 + t + TX * jj) * NY + c);
+        }
+    }
+    __syncthreads();  // TW staged
+    {
         const double2* twx = TW;
         const double2* twy = TW + NX;
         const double2* ky = TW + NX + NY;
-        const double2* kx = a.ktab + z;
-        PassArgs av = a;  // potential tables behind the same opaque offset
-        av.a1 = a.a1 + z;
-        av.ac = a.ac ? a.ac + z : nullptr;
-        av.vtab = a.vtab + z;
+        const double2* kx = a.ktab;
+        const PassArgs& av = a;
 
         // ---------------- X2 stage A: DFT_A1 on the loaded columns, twiddles
 #pragma unroll
@@ -154,8 +128,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                         for (int k1 = 0; k1 < A1; ++k1) L[LY::at(k1 * A2 + t + TX * jj, c)] = vx[q][jj * A1 + k1];
                 }
             }
-            // the loaded registers are free: start fetching the next plane
-            if (r_next < nplanes) load_plane(r_next, vx);
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < QX; ++q) {
@@ -174,19 +146,18 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
             for (int q = 0; q < QX; ++q)
 #pragma unroll
                 for (int e = 0; e < EX; ++e) vb[q][e] = vx[q][e];
-            if (r_next < nplanes) load_plane(r_next, vx);
         }
         // kinetic x phase at (k_x2, y2), then the inverse transform
 #pragma unroll
         for (int q = 0; q < QX; ++q) {
             int c, t;
             if (slot_x(q, &c, &t)) {
-                const double2* kt = kx + (int64_t)c * NX;
+                const double2* kt = kx + c;  // k-major table: [k][y2]
 #pragma unroll
                 for (int ii = 0; ii < IBX; ++ii)
 #pragma unroll
                     for (int k2 = 0; k2 < A2; ++k2) {
-                        double2 f = kt[t + TX * ii + A1 * k2];
+                        double2 f = kt[(t + TX * ii + A1 * k2) * NY];
                         if (a.kconj) f = conjd(f);
                         vb[q][ii * A2 + k2] = cmul(vb[q][ii * A2 + k2], f);
                     }
@@ -372,8 +343,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                     for (int n1 = 0; n1 < B1; ++n1) st<S>(base + row * NY + n1 * B2 + t + TY * jj, vy[q][jj * B1 + n1]);
             }
         }
-        if constexpr (!PERSIST) break;
-        __syncthreads();  // the next plane reuses L
     }
 }
 
@@ -386,3 +355,4 @@ constexpr int plane_threads(int nx, int ny, int tx, int ty) {
 
 }  // namespace dev
 }  // namespace hom4d_impl
+
