@@ -35,7 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-AXES = {0: "x1", 1: "y1", 2: "x2", 3: "y2", 4: "plane(x2,V,y2)", 5: "y1+V"}
+AXES = {0: "x1", 1: "y1", 2: "x2+V", 3: "y2+V", 4: "plane(x2,V,y2)", 5: "y1+V"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mid.json")
 KERNEL_SOURCES = ["paper_1903_02581_amd/csrc/axis_pass.hpp", "paper_1903_02581_amd/csrc/dft_regs.hpp",
                   "paper_1903_02581_amd/csrc/plane_pass.hpp", "paper_1903_02581_amd/csrc/hom4d_host.cpp"]

@@ -181,7 +181,7 @@ int hom4d_grad_end(hom4d* h);
 /* Pass plan.  plan = 0 (default): where a fused kernel is built for (nx, ny)
  * and the precision, one step is three state passes -- x1 line transforms;
  * the (x2, y2) plane of each r1 with X2, V and Y2 fused; y1 line transforms
- * with V fused.  plan = 1: four per-axis passes (x1; x2; V then y1; y2 then V).
+ * with V fused.  plan = 1: four per-axis passes (x1; x2 then V; y1; y2 then V).
  * Both apply the same factors in the same order (Sec. II.C Eq. (evoloperat)).
  * The reverse (adjoint) sweep always uses the per-axis passes.
  * hom4d_pass_plan returns the number of passes per step in use (3 or 4). */
@@ -189,13 +189,12 @@ int hom4d_set_pass_plan(hom4d* h, int32_t plan);
 int hom4d_pass_plan(hom4d* h);
 
 /* Measurement entry point: launch one pass kernel reps times on the bound
- * state, asynchronously.  axis: 0 = x1 and 2 = x2 (kinetic x factor of a full
- * dt), 1 = y1 (potential factor, then kinetic y factor), 3 = y2 (kinetic y
- * factor, then potential factor) -- the kernels of the four-pass plan;
- * 4 = the fused (x2, y2) plane pass and 5 = y1 then potential factor -- the
- * kernels of the three-pass plan (with 0).  Each launch applies a unitary
- * factor, so the state stays normalised but no longer follows the step
- * sequence; the step count is not changed. */
+ * state, asynchronously.  axis: 0 = x1, 1 = y1, 2 = x2 then potential factor,
+ * 3 = y2 then potential factor -- the kernels of the four-pass plan (kinetic
+ * factors of a full dt); 4 = the fused (x2, y2) plane pass and 5 = y1 then
+ * potential factor -- the kernels of the three-pass plan (with 0).  Each
+ * launch applies a unitary factor, so the state stays normalised but no
+ * longer follows the step sequence; the step count is not changed. */
 int hom4d_run_pass(hom4d* h, int32_t axis, int32_t reps);
 
 /* Static string for a status code. */

@@ -410,15 +410,31 @@ AxisKernel pick(int n, int* t) {
     }
 }
 
-// x passes never carry the potential factor; y passes come in table and
-// per-point forms (vk = 1, 2).
+// Variants built: vk = 0 (no potential factor), 1 (table form), 2 (per-point
+// form).  The x1 pass never carries the factor; the reverse (two-state) sweep
+// carries it on the y passes only; the forward plans put it on x2, y1 or y2.
+template <class S, int AXIS, int NST>
+AxisKernel pick_vk(int n, int vk, int* t) {
+    constexpr bool with_v = (NST == 1) ? (AXIS != AX_X1) : (AXIS == AX_Y1 || AXIS == AX_Y2);
+    constexpr bool without_v = (AXIS == AX_X1 || AXIS == AX_X2 || (NST == 1 && AXIS == AX_Y1));
+    if constexpr (with_v) {
+        if (vk == 1) return pick<S, AXIS, NST, 1>(n, t);
+        if (vk == 2) return pick<S, AXIS, NST, 2>(n, t);
+    }
+    if constexpr (without_v) {
+        if (vk == 0) return pick<S, AXIS, NST, 0>(n, t);
+    }
+    *t = 0;
+    return nullptr;
+}
+
 template <class S, int NST>
 AxisKernel pick_axis(int axis, int n, int vk, int* t) {
     switch (axis) {
-        case AX_X1: return pick<S, AX_X1, NST, 0>(n, t);
-        case AX_X2: return pick<S, AX_X2, NST, 0>(n, t);
-        case AX_Y1: return vk == 2 ? pick<S, AX_Y1, NST, 2>(n, t) : pick<S, AX_Y1, NST, 1>(n, t);
-        case AX_Y2: return vk == 2 ? pick<S, AX_Y2, NST, 2>(n, t) : pick<S, AX_Y2, NST, 1>(n, t);
+        case AX_X1: return pick_vk<S, AX_X1, NST>(n, vk, t);
+        case AX_X2: return pick_vk<S, AX_X2, NST>(n, vk, t);
+        case AX_Y1: return pick_vk<S, AX_Y1, NST>(n, vk, t);
+        case AX_Y2: return pick_vk<S, AX_Y2, NST>(n, vk, t);
         default: *t = 0; return nullptr;
     }
 }

@@ -118,7 +118,7 @@ int64_t ilog2_pow2_divisor(int64_t v) {  // largest power of two dividing v
     return v & (-v);
 }
 
-AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad) {
+AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
     AxisPlan p{};
     p.n = (axis == AX_X1 || axis == AX_X2) ? nx : ny;
     FftShape sh;
@@ -128,7 +128,10 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad) {
     p.nlines = nxy * nxy / p.n;
     int64_t w = 256 / sh.t;
     if (sh.n2 > 1) {
-        const int64_t cap = (65536 - 2 * p.n * 16) / ((int64_t)nst * p.n * 16) - 1;
+        // LDS per block: 64 KB for complex128 storage (W = 16 lines already gives
+        // 256-byte runs), 80 KB for complex64 (two blocks per CU, W = 32 on n = 128)
+        const int64_t budget = mixed ? 81920 : 65536;
+        const int64_t cap = (budget - 2 * p.n * 16) / ((int64_t)nst * p.n * 16) - 1;
         while (w > cap) w >>= 1;
     }
     w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
@@ -301,7 +304,7 @@ struct GradCtx {
 int run_pass(hom4d* h, int axis, KTab kt, int vmode, int nst, void* lam, bool reverse, int gflags,
              const GradCtx* g) {
     const hom4d_cfg& c = h->cfg;
-    AxisPlan p = plan_axis(axis, c.nx, c.ny, nst, nst == 2);
+    AxisPlan p = plan_axis(axis, c.nx, c.ny, nst, nst == 2, h->mixed);
     PassArgs a{};
     a.psi = h->psi;
     a.lam = lam;
@@ -385,10 +388,29 @@ int run_steps_plane(hom4d* h, int64_t n) {
     return run_pass(h, AX_X2, KX_HALF, 0, 1, nullptr, false, 0, nullptr);
 }
 
+// n whole forward steps in four per-axis passes, the potential factor as the
+// epilogue of the x2 and y2 passes:  X1 | X2, V | Y1 | Y2, V | X1 ...
+int run_steps_axis(hom4d* h, int64_t n) {
+    int rc;
+    if ((rc = run_pass(h, AX_X1, KX_HALF, 0, 1, nullptr, false, 0, nullptr))) return rc;
+    if ((rc = run_pass(h, AX_X2, KX_HALF, 2, 1, nullptr, false, 0, nullptr))) return rc;
+    for (int64_t i = 0; i < n; ++i) {
+        const bool last = i == n - 1;
+        if ((rc = run_pass(h, AX_Y1, KY_FULL, 0, 1, nullptr, false, 0, nullptr))) return rc;
+        if ((rc = run_pass(h, AX_Y2, KY_FULL, 2, 1, nullptr, false, 0, nullptr))) return rc;
+        const KTab kx = last ? KX_HALF : KX_FULL;
+        if ((rc = run_pass(h, AX_X1, kx, 0, 1, nullptr, false, 0, nullptr))) return rc;
+        if ((rc = run_pass(h, AX_X2, kx, last ? 0 : 2, 1, nullptr, false, 0, nullptr))) return rc;
+    }
+    return HOM4D_OK;
+}
+
 // n whole steps with merged X halves; the state is closed at the end.
 int run_steps(hom4d* h, int64_t n, int nst, void* lam, bool reverse, const GradCtx* g) {
     if (n <= 0) return HOM4D_OK;
-    if (nst == 1 && !reverse && use_plane(h)) return run_steps_plane(h, n);
+    if (nst == 1 && !reverse) return use_plane(h) ? run_steps_plane(h, n) : run_steps_axis(h, n);
+    // reverse (dual-state) sweep: X1 | X2 | V, Y1 | Y2, V -- the gradient marginals of each
+    // potential factor are taken by the passes on either side of it
     const bool gr = nst == 2;
     int rc;
     if ((rc = run_pass(h, AX_X1, KX_HALF, 0, nst, lam, reverse, gr ? G_GB : 0, g))) return rc;
@@ -404,6 +426,9 @@ int run_steps(hom4d* h, int64_t n, int nst, void* lam, bool reverse, const GradC
     }
     return HOM4D_OK;
 }
+
+
+
 
 int fetch_reduction(hom4d* h, int width, double* out) {
     HIP_TRY(launch_reduce_parts(h->red_part, h->red_blocks, width, h->red_out, h->stream));
@@ -833,8 +858,10 @@ int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs, voi
     if (!h->rec) return fail(HOM4D_ESTATE, "no recorded forward run (hom4d_grad_begin + hom4d_step)");
     if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
     const hom4d_cfg& c = h->cfg;
-    const AxisPlan px1 = plan_axis(AX_X1, c.nx, c.ny, 2, true), px2 = plan_axis(AX_X2, c.nx, c.ny, 2, true);
-    const AxisPlan py1 = plan_axis(AX_Y1, c.nx, c.ny, 2, true), py2 = plan_axis(AX_Y2, c.nx, c.ny, 2, true);
+    const AxisPlan px1 = plan_axis(AX_X1, c.nx, c.ny, 2, true, h->mixed);
+    const AxisPlan px2 = plan_axis(AX_X2, c.nx, c.ny, 2, true, h->mixed);
+    const AxisPlan py1 = plan_axis(AX_Y1, c.nx, c.ny, 2, true, h->mixed);
+    const AxisPlan py2 = plan_axis(AX_Y2, c.nx, c.ny, 2, true, h->mixed);
     const int64_t nb_x1 = px1.nlines / px1.W, nb_x2 = px2.nlines / px2.W, nb_y2 = py2.nlines / py2.W;
     const int64_t len_m_x1 = px1.nlines, len_m_y1 = py1.nlines;
     const size_t need = (size_t)(nb_x1 + nb_x2 + len_m_x1 + len_m_y1 + nb_x2 + nb_y2 + h->nxy);
@@ -911,7 +938,7 @@ int hom4d_run_pass(hom4d* h, int32_t axis, int32_t reps) {
     if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
     if (!h->have_v) return fail(HOM4D_ESTATE, "no potential set (hom4d_set_potential)");
     const KTab kt = (axis == AX_X1 || axis == AX_X2) ? KX_FULL : KY_FULL;
-    const int vmode = axis == AX_Y1 ? 1 : (axis == AX_Y2 ? 2 : 0);
+    const int vmode = (axis == AX_X2 || axis == AX_Y2) ? 2 : 0;  // the four-pass plan's kernels
     for (int32_t r = 0; r < reps; ++r) {
         int rc = run_pass(h, axis, kt, vmode, 1, nullptr, false, 0, nullptr);
         if (rc) return rc;

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
+#include <unordered_set>
 
 #include "axis_pass.hpp"
 #include "hom4d_internal.hpp"
@@ -200,14 +202,26 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
                        hipStream_t s) {
     int t = 0;
     AxisKernel fn = nullptr;
-    const int vk = a.vdirect ? 2 : 1;
+    const int vk = a.vmode == 0 ? 0 : (a.vdirect ? 2 : 1);
     if (!mixed)
         fn = (nst == 2) ? pick_axis_f64_2(axis, n, vk, &t) : pick_axis_f64_1(axis, n, vk, &t);
     else
         fn = (nst == 2) ? pick_axis_f32_2(axis, n, vk, &t) : pick_axis_f32_1(axis, n, vk, &t);
     if (!fn || a.W <= 0 || nlines % a.W != 0) return hipErrorInvalidValue;
     const int64_t nblocks = nlines / a.W;
-    if (nblocks > 0x7fffffff || t * a.W > 256) return hipErrorInvalidValue;
+    if (nblocks > 0x7fffffff || t * a.W > 256 || lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    if (lds_bytes > 64 * 1024) {
+        // dynamic LDS above 64 KB has to be enabled per kernel, once
+        static std::mutex mu;
+        static std::unordered_set<const void*> raised;
+        std::lock_guard<std::mutex> lock(mu);
+        const void* key = reinterpret_cast<const void*>(fn);
+        if (!raised.count(key)) {
+            hipError_t e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+            raised.insert(key);
+        }
+    }
     hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3(t * a.W), lds_bytes, s, a);
     return hipGetLastError();
 }
