@@ -151,6 +151,17 @@ int hom4d_set_norm_tol(hom4d* h, double tol);
 int hom4d_entanglement(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1,
                        const int32_t* ix2, int32_t n2, int32_t jy2, double* s_out);
 
+/* Unconditional (marginal) probability of electron 1 (Sec. III.A, Fig. 3(b)
+ * caption): out[x1][y1] = sum over (x2, y2) of |Psi(x1, y1, x2, y2)|^2, host
+ * [nx][ny] FP64, FP64 accumulation in a fixed order.  Synchronises. */
+int hom4d_marginal(hom4d* h, double* out);
+
+/* Conditional probability of electron 1 with electron 2 at the grid point
+ * (ix2, jy2) (Sec. II.A, Fig. 2 caption): out[x1][y1] = |Psi(x1, y1, ix2, jy2)|^2,
+ * host [nx][ny] FP64, not renormalised.  EINVAL on an index out of range.
+ * Synchronises. */
+int hom4d_conditional(hom4d* h, int32_t ix2, int32_t jy2, double* out);
+
 /* Gather the (n1 x n2) slice above into host memory (interleaved complex128),
  * unnormalised.  Synchronises. */
 int hom4d_gather_slice(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1,

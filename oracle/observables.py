@@ -15,7 +15,13 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   the paper's formula drops the minus sign and has an index typo).  Computed
   from the singular values of phi: the eigenvalues of rho are their squares.
 
-Pins: P_TT + P_TB + P_BT + P_BB = norm and P_TB = P_BT for exchange-symmetric
+* Marginal and conditional one-electron densities (Fig. 3(b), Fig. 2 captions).
+
+Pins: the marginal of a product state is |psi_a|^2 <b|b>; for the Slater
+determinant the marginal has the closed form (|a|^2 + |b|^2 - 2 Re(conj(a) b
+<b|a>)) / (2 (1 - |<a|b>|^2)) for normalised a, b; the conditional probability
+vanishes at r1 = r2* (Pauli node of the Fig. 2 caption);
+P_TT + P_TB + P_BT + P_BB = norm and P_TB = P_BT for exchange-symmetric
 states (invariants); entanglement of a product state is 0 and of a two-term
 Schmidt state with orthonormal factors is ln 2; the SVD route agrees with the
 eigenvalues of rho computed by numpy.linalg.eigvalsh.
@@ -41,6 +47,18 @@ def observables(psi: np.ndarray, w_top: np.ndarray) -> dict:
     p_bb = float(np.sum((1.0 - w1) * (1.0 - w2) * dens))
     return dict(norm=float(np.sum(dens)), p_tt=p_tt, p_tb=p_tb, p_bt=p_bt, p_bb=p_bb,
                 p_b=p_tt + p_bb, p_ab=p_tb + p_bt)
+
+
+def marginal(psi: np.ndarray) -> np.ndarray:
+    """Unconditional probability of electron 1 (Sec. III.A, Fig. 3(b) caption):
+    P(x1, y1) = sum_{x2, y2} |Psi|^2."""
+    return np.sum(np.abs(psi) ** 2, axis=(2, 3))
+
+
+def conditional(psi: np.ndarray, ix2: int, jy2: int) -> np.ndarray:
+    """Conditional probability of electron 1 with electron 2 at (x2*, y2*)
+    (Sec. II.A, Fig. 2 caption): |Psi(x1, y1, x2*, y2*)|^2, not renormalised."""
+    return np.abs(psi[:, :, ix2, jy2]) ** 2
 
 
 def entanglement(psi: np.ndarray, ix1, jy1: int, ix2, jy2: int) -> float:

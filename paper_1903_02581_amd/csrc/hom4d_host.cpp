@@ -765,6 +765,32 @@ int hom4d_observables(hom4d* h, const double* w_top, hom4d_obs* out) {
     return HOM4D_OK;
 }
 
+int hom4d_marginal(hom4d* h, double* out) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!out) return fail(HOM4D_EINVAL, "out is NULL");
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    // the reduction partial buffer has room for red_blocks * 8 >= nx*ny doubles only if
+    // nx*ny <= 8 * red_blocks; the slice buffer (256*256 complex) always does
+    double* dst = reinterpret_cast<double*>(h->slice_dev);
+    HIP_TRY(launch_marginal(h->psi, h->mixed, h->nxy, dst, h->stream));
+    HIP_TRY(hipMemcpyAsync(out, dst, h->nxy * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return HOM4D_OK;
+}
+
+int hom4d_conditional(hom4d* h, int32_t ix2, int32_t jy2, double* out) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!out) return fail(HOM4D_EINVAL, "out is NULL");
+    if (ix2 < 0 || ix2 >= h->cfg.nx || jy2 < 0 || jy2 >= h->cfg.ny)
+        return fail(HOM4D_EINVAL, "(ix2, jy2) = (%d, %d) out of range", ix2, jy2);
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    double* dst = reinterpret_cast<double*>(h->slice_dev);
+    HIP_TRY(launch_conditional(h->psi, h->mixed, h->nxy, ix2 * h->cfg.ny + jy2, dst, h->stream));
+    HIP_TRY(hipMemcpyAsync(out, dst, h->nxy * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return HOM4D_OK;
+}
+
 int hom4d_gather_slice(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1, const int32_t* ix2, int32_t n2,
                        int32_t jy2, double* out) {
     if (!h) return fail(HOM4D_EINVAL, "handle is NULL");

@@ -79,6 +79,8 @@ hipError_t launch_reduce_parts(const double* part, int nparts, int width, double
 hipError_t launch_gather(const void* psi, bool mixed, const int32_t* ix1, int n1, int jy1,
                          const int32_t* ix2, int n2, int jy2, int nx, int ny, double2* out,
                          hipStream_t s);
+hipError_t launch_marginal(const void* psi, bool mixed, int nxy, double* out, hipStream_t s);
+hipError_t launch_conditional(const void* psi, bool mixed, int nxy, int r2, double* out, hipStream_t s);
 hipError_t launch_c128_to_c64(const double2* in, float2* out, int64_t count, hipStream_t s);
 hipError_t launch_c64_to_c128(const float2* in, double2* out, int64_t count, hipStream_t s);
 hipError_t launch_grad_finish(const double* m_x2, int bpr_x2, const double* m_y2, int bpr_y2,

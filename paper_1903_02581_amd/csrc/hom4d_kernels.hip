@@ -148,6 +148,30 @@ __global__ void k_gather(const S* psi, const int32_t* ix1, int n1, int jy1, cons
     out[idx] = ld<S>(psi + off);
 }
 
+// out[r1] = sum_r2 |psi(r1, r2)|^2: one block per r1 over its contiguous plane.
+template <class S>
+__global__ void k_marginal(const S* psi, int nxy, double* out) {
+    __shared__ double red[256];
+    const int r1 = blockIdx.x;
+    const S* row = psi + (int64_t)r1 * nxy;
+    double acc = 0.0;
+    for (int r2 = threadIdx.x; r2 < nxy; r2 += blockDim.x) {
+        const double2 p = ld<S>(row + r2);
+        acc += p.x * p.x + p.y * p.y;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) out[r1] = s;
+}
+
+// out[r1] = |psi(r1, r2)|^2 for one fixed r2.
+template <class S>
+__global__ void k_conditional(const S* psi, int nxy, int r2, double* out) {
+    const int r1 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r1 >= nxy) return;
+    const double2 p = ld<S>(psi + (int64_t)r1 * nxy + r2);
+    out[r1] = p.x * p.x + p.y * p.y;
+}
+
 __global__ void k_c128_to_c64(const double2* in, float2* out, int64_t count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         out[i] = make_float2((float)in[i].x, (float)in[i].y);
@@ -293,6 +317,23 @@ hipError_t launch_gather(const void* psi, bool mixed, const int32_t* ix1, int n1
     else
         hipLaunchKernelGGL(k_gather<double2>, dim3(nb), dim3(256), 0, s, (const double2*)psi, ix1, n1, jy1, ix2, n2,
                            jy2, nx, ny, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_marginal(const void* psi, bool mixed, int nxy, double* out, hipStream_t s) {
+    if (mixed)
+        hipLaunchKernelGGL(k_marginal<float2>, dim3(nxy), dim3(256), 0, s, (const float2*)psi, nxy, out);
+    else
+        hipLaunchKernelGGL(k_marginal<double2>, dim3(nxy), dim3(256), 0, s, (const double2*)psi, nxy, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_conditional(const void* psi, bool mixed, int nxy, int r2, double* out, hipStream_t s) {
+    const int nb = (nxy + 255) / 256;
+    if (mixed)
+        hipLaunchKernelGGL(k_conditional<float2>, dim3(nb), dim3(256), 0, s, (const float2*)psi, nxy, r2, out);
+    else
+        hipLaunchKernelGGL(k_conditional<double2>, dim3(nb), dim3(256), 0, s, (const double2*)psi, nxy, r2, out);
     return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ STATUS = {0: "HOM4D_OK", -1: "HOM4D_EINVAL", -2: "HOM4D_EUNBOUND", -3: "HOM4D_ES
 EXPORTS = ["hom4d_create", "hom4d_destroy", "hom4d_validate_cfg", "hom4d_state_bytes",
            "hom4d_bind_state", "hom4d_set_potential", "hom4d_set_field", "hom4d_init_state",
            "hom4d_load_state", "hom4d_store_state", "hom4d_step", "hom4d_observables",
-           "hom4d_set_norm_tol", "hom4d_entanglement", "hom4d_gather_slice", "hom4d_grad_begin",
+           "hom4d_set_norm_tol", "hom4d_entanglement", "hom4d_gather_slice", "hom4d_marginal",
+           "hom4d_conditional", "hom4d_grad_begin",
            "hom4d_grad_backward", "hom4d_grad_end", "hom4d_run_pass", "hom4d_set_pass_plan",
            "hom4d_pass_plan", "hom4d_strerror",
            "hom4d_last_error"]
@@ -83,6 +84,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "hom4d_set_norm_tol": ([vp, c_double], c_int),
         "hom4d_entanglement": ([vp, i32p, c_int32, c_int32, i32p, c_int32, c_int32, dp], c_int),
         "hom4d_gather_slice": ([vp, i32p, c_int32, c_int32, i32p, c_int32, c_int32, dp], c_int),
+        "hom4d_marginal": ([vp, dp], c_int),
+        "hom4d_conditional": ([vp, c_int32, c_int32, dp], c_int),
         "hom4d_grad_begin": ([vp, c_int32, vp, c_size_t], c_int),
         "hom4d_grad_backward": ([vp, dp, dp, vp, dp, dp, dp], c_int),
         "hom4d_grad_end": ([vp], c_int),
@@ -246,6 +249,19 @@ class Propagator:
                                                 b.ctypes.data_as(POINTER(c_int32)), len(b),
                                                 int(jy2), _dptr(out.view(np.float64))),
                     "gather_slice")
+        return out
+
+    def marginal(self) -> np.ndarray:
+        """P(x1, y1) = sum over (x2, y2) of |Psi|^2, shape [nx, ny]."""
+        out = np.empty((self.nx, self.ny), dtype=np.float64)
+        self._check(self.lib.hom4d_marginal(self.h, _dptr(out)), "marginal")
+        return out
+
+    def conditional(self, ix2: int, jy2: int) -> np.ndarray:
+        """|Psi(x1, y1, ix2, jy2)|^2 over (x1, y1), shape [nx, ny]."""
+        out = np.empty((self.nx, self.ny), dtype=np.float64)
+        self._check(self.lib.hom4d_conditional(self.h, int(ix2), int(jy2), _dptr(out)),
+                    "conditional")
         return out
 
     # ---------------------------------------------------------------- adjoint

@@ -184,3 +184,22 @@ def test_watchdog_and_errors():
     with pytest.raises(Hom4dError):
         p.observables(w.w_top, check=True)
     p.close()
+
+
+def test_marginal_and_conditional_densities():
+    from paper_1903_02581_amd import Propagator
+    w = preset("tiny")
+    announce("marginal / conditional densities tiny")
+    for prec, tol in (("fp64", 1e-13), ("mixed", 1e-6)):
+        p = Propagator.from_workload(w, precision=prec)
+        p.step(40)
+        psi = p.store_state()
+        m = p.marginal()
+        assert np.max(np.abs(m - O.marginal(psi))) <= tol * np.max(m)
+        assert abs(m.sum() - 1.0) <= (1e-12 if prec == "fp64" else 1e-5)
+        for (ix2, jy2) in [(3, 11), (12, 4)]:
+            c = p.conditional(ix2, jy2)
+            assert np.array_equal(c, O.conditional(psi, ix2, jy2)) or \
+                np.max(np.abs(c - O.conditional(psi, ix2, jy2))) <= 1e-15
+            assert c[ix2, jy2] <= 1e-25       # Pauli node at r1 = r2*
+        p.close()

@@ -325,3 +325,25 @@ def test_p8_entanglement_special_cases():
     lam = np.linalg.eigvalsh(phi @ phi.conj().T)
     lam = lam[lam > 1e-300]
     assert abs(O.entanglement(psi, ix, 3, ix, 0) + np.sum(lam * np.log(lam))) < 1e-12
+
+
+# ----------------------------------------------------- marginal / conditional densities
+
+def test_marginal_and_conditional_closed_forms():
+    rng = np.random.default_rng(5)
+    nx, ny = 6, 5
+    a = rng.standard_normal((nx, ny)) + 1j * rng.standard_normal((nx, ny))
+    b = rng.standard_normal((nx, ny)) + 1j * rng.standard_normal((nx, ny))
+    a /= np.linalg.norm(a)
+    b /= np.linalg.norm(b)
+    prod = O.init_state(a, b, 0)
+    assert np.allclose(O.marginal(prod), np.abs(a) ** 2, atol=1e-15)
+    slater = O.init_state(a, b, -1)
+    ab = np.vdot(a, b)                      # <a|b>
+    ref = (np.abs(a) ** 2 + np.abs(b) ** 2 - 2 * np.real(np.conj(a) * b * np.conj(ab))) \
+        / (2 * (1 - abs(ab) ** 2))
+    assert np.allclose(O.marginal(slater), ref, atol=1e-14)
+    assert abs(O.marginal(slater).sum() - 1.0) < 1e-14
+    c = O.conditional(slater, 2, 3)
+    assert c[2, 3] < 1e-30                  # Pauli node at r1 = r2*
+    assert np.allclose(O.conditional(prod, 2, 3), np.abs(a) ** 2 * abs(b[2, 3]) ** 2, atol=1e-15)
