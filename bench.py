@@ -50,11 +50,12 @@ def kernel_hash() -> str:
 
 
 PLAN = 0
+COULOMB_MODE = "table"
 
 
 def make_prop(w, precision):
     from paper_1903_02581_amd import Propagator
-    p = Propagator.from_workload(w, precision=precision)
+    p = Propagator.from_workload(w, precision=precision, coulomb_mode=COULOMB_MODE)
     p.set_pass_plan(PLAN)
     return p
 
@@ -186,6 +187,8 @@ def main():
                     help="skip the other workloads' throughput and the adjoint timing")
     ap.add_argument("--workload", default="mid",
                     help="named workload for the timed run (default: the 64x64 case, run 0 of its sweep)")
+    ap.add_argument("--coulomb-mode", default="table", choices=["table", "direct"],
+                    help="potential factor from difference tables (default) or per point")
     ap.add_argument("--plan", type=int, default=0, choices=[0, 1],
                     help="0: fused three-pass steps (default), 1: four per-axis passes")
     ap.add_argument("--profile-passes", type=int, default=0,
@@ -199,8 +202,9 @@ def main():
 
     import torch
     from workloads import preset
-    global PLAN
+    global PLAN, COULOMB_MODE
     PLAN = args.plan
+    COULOMB_MODE = args.coulomb_mode
 
     w = preset("mid", run=0) if args.workload == "mid" else preset(args.workload)
     P = w.points
