@@ -47,10 +47,11 @@ def test_three_pass_vs_oracle(nx, ny, steps):
 
 
 @pytest.mark.parametrize("mode", ["table", "direct"])
-def test_three_pass_mixed_and_direct(mode):
+@pytest.mark.parametrize("nx,ny,steps", [(48, 48, 30), (64, 64, 6), (16, 48, 30)])
+def test_three_pass_mixed_and_direct(mode, nx, ny, steps):
     from paper_1903_02581_amd import Propagator
-    w = _w(48, 48, 30)
-    announce(f"plane mixed/{mode} 48x48 steps=30")
+    w = _w(nx, ny, steps)
+    announce(f"plane mixed/{mode} {nx}x{ny} steps={steps}")
     res = {}
     for prec in ("fp64", "mixed"):
         p = Propagator.from_workload(w, precision=prec, coulomb_mode=mode)
