@@ -113,11 +113,11 @@ def cpu_baseline(w, budget_s):
     return n, el
 
 
-def config_throughput(name, precision, steps, plan=None):
+def config_throughput(name, precision, steps, plan=None, **overrides):
     """Short timed run of another named workload (same kernels, other sizes)."""
     import torch
     from workloads import preset
-    w = preset(name)
+    w = preset(name, **overrides)
     p = make_prop(w, precision)
     if plan is not None:
         p.set_pass_plan(plan)
@@ -127,7 +127,8 @@ def config_throughput(name, precision, steps, plan=None):
     p.step(steps)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    out = {"workload": name, "nx": w.nx, "ny": w.ny, "points": w.points, "precision": precision,
+    out = {"workload": name + "".join(f",{k}={v}" for k, v in overrides.items()),
+           "nx": w.nx, "ny": w.ny, "points": w.points, "precision": precision,
            "steps": steps, "passes_per_step": p.passes_per_step,
            "gp_steps_per_s": w.points * steps / sec, "ms_per_step": sec / steps * 1e3}
     sbytes = 16 if precision == "fp64" else 8
@@ -270,6 +271,8 @@ def main():
                 config_throughput("full", "mixed", 50),
                 config_throughput("diff", "fp64", 500),
                 config_throughput("tiny", "fp64", 2000),
+                config_throughput("qpc", "fp64", 300, coulomb_c=1.0),
+                config_throughput("qpc", "mixed", 300, coulomb_c=1.0),
             ],
             "adjoint": [adjoint_throughput("fp64"), adjoint_throughput("mixed")],
         }

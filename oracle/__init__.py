@@ -22,5 +22,6 @@ Parity status per function is listed in each module docstring.
 from .splitstep import (Grid, make_grid, theta_x, theta_y, theta_v, apply_x, apply_y,  # noqa
                         apply_v, strang_step, propagate, init_state, propagate_2d,
                         strang_step_2d)
-from .observables import observables, entanglement, region_weights_4d, marginal, conditional  # noqa
+from .observables import (observables, entanglement, region_weights_4d, marginal, conditional,  # noqa
+                          orbital_observables)
 from .adjoint import loss_and_grad_stored, grad_fd  # noqa

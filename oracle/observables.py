@@ -16,8 +16,15 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   from the singular values of phi: the eigenvalues of rho are their squares.
 
 * Marginal and conditional one-electron densities (Fig. 3(b), Fig. 2 captions).
+* Region probabilities of a two-electron state built from two orbitals
+  (Sec. II.C Eq. (twopstate) with symmetry s): without the two-body term the
+  4D propagation keeps this form with each orbital propagated in 2D, so the
+  sums over configuration space reduce to one-electron matrix elements:
+      sum w1 w2 |a1 b2 + s b1 a2|^2 = <a|w1|a><b|w2|b> + s^2 <b|w1|b><a|w2|a>
+                                      + 2 s Re(<a|w1|b><b|w2|a>).
 
-Pins: the marginal of a product state is |psi_a|^2 <b|b>; for the Slater
+Pins: the orbital form of the region probabilities equals observables() of the
+4D state init_state(a, b, s) for random orbitals and s = -1, 0, +1; the marginal of a product state is |psi_a|^2 <b|b>; for the Slater
 determinant the marginal has the closed form (|a|^2 + |b|^2 - 2 Re(conj(a) b
 <b|a>)) / (2 (1 - |<a|b>|^2)) for normalised a, b; the conditional probability
 vanishes at r1 = r2* (Pauli node of the Fig. 2 caption);
@@ -47,6 +54,28 @@ def observables(psi: np.ndarray, w_top: np.ndarray) -> dict:
     p_bb = float(np.sum((1.0 - w1) * (1.0 - w2) * dens))
     return dict(norm=float(np.sum(dens)), p_tt=p_tt, p_tb=p_tb, p_bt=p_bt, p_bb=p_bb,
                 p_b=p_tt + p_bb, p_ab=p_tb + p_bt)
+
+
+def orbital_observables(a: np.ndarray, b: np.ndarray, w_top: np.ndarray, sym: int) -> dict:
+    """Region probabilities of the normalised state a(r1) b(r2) + sym b(r1) a(r2)
+    from one-electron matrix elements (no 4D array is formed)."""
+    a = np.asarray(a, dtype=np.complex128).ravel()
+    b = np.asarray(b, dtype=np.complex128).ravel()
+    wt = np.asarray(w_top, dtype=np.float64).ravel()
+    wb = 1.0 - wt
+    s = float(sym)
+
+    def pair(w1, w2):
+        return (np.vdot(a, w1 * a).real * np.vdot(b, w2 * b).real
+                + s * s * np.vdot(b, w1 * b).real * np.vdot(a, w2 * a).real
+                + 2.0 * s * np.real(np.vdot(a, w1 * b) * np.vdot(b, w2 * a)))
+
+    one = np.ones_like(wt)
+    norm = pair(one, one)
+    p_tt, p_tb, p_bt, p_bb = (pair(wt, wt) / norm, pair(wt, wb) / norm, pair(wb, wt) / norm,
+                              pair(wb, wb) / norm)
+    return dict(norm=1.0, p_tt=p_tt, p_tb=p_tb, p_bt=p_bt, p_bb=p_bb, p_b=p_tt + p_bb,
+                p_ab=p_tb + p_bt)
 
 
 def marginal(psi: np.ndarray) -> np.ndarray:

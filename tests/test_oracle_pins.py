@@ -347,3 +347,27 @@ def test_marginal_and_conditional_closed_forms():
     c = O.conditional(slater, 2, 3)
     assert c[2, 3] < 1e-30                  # Pauli node at r1 = r2*
     assert np.allclose(O.conditional(prod, 2, 3), np.abs(a) ** 2 * abs(b[2, 3]) ** 2, atol=1e-15)
+
+
+# ---------------------------------------- region probabilities from two orbitals
+
+@pytest.mark.parametrize("sym", [-1, 0, 1])
+def test_orbital_observables_brute_force(sym):
+    # the one-electron matrix-element form against the explicit 4D sum over
+    # configuration space of the normalised state built by init_state
+    rng = np.random.default_rng(11 + sym)
+    nx, ny = 5, 4
+    a = rng.standard_normal((nx, ny)) + 1j * rng.standard_normal((nx, ny))
+    b = rng.standard_normal((nx, ny)) + 1j * rng.standard_normal((nx, ny))
+    a /= np.linalg.norm(a)
+    b /= np.linalg.norm(b)
+    w = rng.uniform(0.0, 1.0, (nx, ny))
+    psi = O.init_state(a, b, sym)
+    d = np.abs(psi) ** 2
+    w1, w2 = w[:, :, None, None], w[None, None, :, :]
+    brute = dict(p_tt=np.sum(d * w1 * w2), p_tb=np.sum(d * w1 * (1 - w2)),
+                 p_bt=np.sum(d * (1 - w1) * w2), p_bb=np.sum(d * (1 - w1) * (1 - w2)))
+    got = O.orbital_observables(a, b, w, sym)
+    for k, v in brute.items():
+        assert abs(got[k] - v) < 1e-14, (k, got[k], v)
+    assert abs(got["p_b"] - brute["p_tt"] - brute["p_bb"]) < 1e-14

@@ -107,6 +107,29 @@ def saddle_potential(x: np.ndarray, y: np.ndarray, v0: float, v1: float,
     return v0 * np.exp(-X ** 2 / sx ** 2) - v1 * np.exp(-Y ** 2 / sy ** 2) + walls
 
 
+def fermi(u: np.ndarray) -> np.ndarray:
+    """Fermi step 1 / (exp(u / tau) + 1) of the barrier smoothness tau = 3 nm: 1 for u << 0."""
+    return 0.5 * (1.0 - np.tanh(0.5 * u / WALL_SMOOTH_NM))
+
+
+def fermi_block_qpc(x: np.ndarray, y: np.ndarray, ly: float, gap: float,
+                    half_len: float) -> np.ndarray:
+    """V(x, y) in meV: Fermi walls along y plus a constriction made of two
+    Fermi-function blocks of height V_b (Sec. II.C Eq. (pot_xy)).
+
+    Each block is a product of Fermi steps, as in the paper, rotated to this
+    geometry (propagation along x): one hangs from the top wall over
+    |x| < half_len down to y = +gap/2, the other rises from the bottom wall to
+    y = -gap/2, leaving an opening of width gap between them."""
+    X = x[:, None]
+    Y = y[None, :]
+    yw = WALL_POS_FRAC * ly
+    walls = WALL_HEIGHT_MEV * (fermi(yw - Y) + fermi(yw + Y))
+    fx = fermi(-X - half_len) * fermi(X - half_len)
+    blocks = WALL_HEIGHT_MEV * fx * (fermi(0.5 * gap - Y) + fermi(Y + 0.5 * gap))
+    return walls + blocks
+
+
 def top_weights(nx: int, ny: int, ly: float) -> np.ndarray:
     """Weight of each single-particle grid point in the top region T = {y > 0}."""
     y = grid_x(ny, ly)
@@ -164,14 +187,21 @@ def build(name: str, nx: int, ny: int, lx: float, ly: float, *, b_tesla: float,
           sym: int = -1, v0: float = 4.0, v1: float = 2.0, sx: float = 30.0,
           sy: float = 60.0, sigma_x: float = 20.0, seed: int = 0,
           mstar_rel: float = 0.067, eps_r: float = 12.9, ckpt_every: int = 100,
-          e_above_lll: float = 2.0) -> Workload:
+          e_above_lll: float = 2.0, qpc_gap_nm: float | None = None,
+          qpc_half_nm: float = 15.0) -> Workload:
+    """qpc_gap_nm set: the beam splitter is the Fermi-block constriction
+    (fermi_block_qpc) instead of the saddle, and v0, v1, sx, sy are unused."""
     x = grid_x(nx, lx)
     y = grid_x(ny, ly)
     dx = lx / nx
     jit = np.random.default_rng(seed).uniform(-0.5 * dx, 0.5 * dx, 2)
     xa = -0.25 * lx + jit[0]
     xb = +0.25 * lx + jit[1]
-    v = saddle_potential(x, y, v0, v1, sx, sy, ly)
+    if qpc_gap_nm is None:
+        v = saddle_potential(x, y, v0, v1, sx, sy, ly)
+    else:
+        v = fermi_block_qpc(x, y, ly, qpc_gap_nm, qpc_half_nm)
+        v0 = v1 = 0.0
     # transverse potential seen by each packet: the column of V nearest its start
     ia = int(np.argmin(np.abs(x - xa)))
     ib = int(np.argmin(np.abs(x - xb)))
@@ -184,7 +214,8 @@ def build(name: str, nx: int, ny: int, lx: float, ly: float, *, b_tesla: float,
                     coulomb_c=coulomb_c, sym=sym, v0=v0, v1=v1, sx=sx, sy=sy,
                     sigma_x=sigma_x, seed=seed, v_table=v, psi_a=psi_a, psi_b=psi_b,
                     w_top=top_weights(nx, ny, ly), ckpt_every=ckpt_every,
-                    info=dict(xa=xa, xb=xb, alpha=ia_info, beta=ib_info))
+                    info=dict(xa=xa, xb=xb, alpha=ia_info, beta=ib_info, qpc_gap_nm=qpc_gap_nm,
+                              qpc_half_nm=qpc_half_nm))
 
 
 def mid_sweep():
@@ -226,8 +257,28 @@ def _fp64_128(seed=0, **kw):
                  soft_nm=2.0, sigma_x=10.0, seed=seed, **kw)
 
 
+# Resolving beam-splitter workload.  At 5 T (l_B = 11.47 nm) the grid keeps
+# nx >= flux count lx*ly / (2 pi l_B^2) = 124 (every Landau-gauge guiding centre
+# y0 = k_x l_B^2 across the strip is a grid wave number) and dy = 4 nm < l_B / 2.
+# The packets sit 5 meV above the lowest Landau level (group velocity ~80
+# nm/ps here; at 2 meV the packets of this wall profile are slow and strongly
+# dispersive), and the opening is set so that a sigma = 15 nm packet leaves
+# the constriction half transmitted.  The run ends before the reflected parts
+# wrap around the periodic x direction back into the constriction.
+QPC_GAP_NM = 60.2
+
+
+def _qpc(seed=0, **kw):
+    kw.setdefault("sigma_x", 15.0)
+    kw.setdefault("qpc_gap_nm", QPC_GAP_NM)
+    kw.setdefault("e_above_lll", 5.0)
+    kw.setdefault("coulomb_c", 0.0)
+    return build("qpc", 128, 64, 400.0, 256.0, b_tesla=5.0, dt_fs=1.0, steps=2500,
+                 soft_nm=1.0, seed=seed, **kw)
+
+
 PRESETS = {"tiny": _tiny, "mid": _mid, "mixed": _mixed, "diff": _diff, "full": _full,
-           "fp64_128": _fp64_128}
+           "fp64_128": _fp64_128, "qpc": _qpc}
 
 
 def preset(name: str, seed: int = 0, **overrides) -> Workload:
