@@ -1,0 +1,8 @@
+// Instantiations of the three-stage per-axis pass for float2 storage.
+#include "axis3_pass.hpp"
+
+namespace hom4d_impl {
+dev::AxisKernel pick_axis3_f32(int axis, int n, int vk, int* t) {
+    return dev::pick_axis3<float2>(axis, n, vk, t);
+}
+}  // namespace hom4d_impl

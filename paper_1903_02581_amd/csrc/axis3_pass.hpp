@@ -1,0 +1,220 @@
+// Per-axis pass for the long lines (n = 96, 128) of the forward step:
+// the same transform -> kinetic phase -> inverse round trip as k_axis
+// (Sec. II.C Eq. (evoloperat); kinetic terms of Appendix A), with the line
+// transform factored into three radix stages instead of two, so that every
+// thread holds 8 (or 12) elements instead of 16 (or 24) and the kernels keep
+// enough waves resident to stream HBM.  (For n = 256 the three-stage form
+// needs 32 threads per line, which leaves too few lines per block for wide
+// HBM runs on the strided axes; the two-stage kernel stays faster there.)
+//
+// Line of n = R1 R2 R3 points, element m = n1 (R2 R3) + n2 R3 + j3, handled by T
+// threads.  Forward:
+//   stage A   DFT_R1 over n1 for each column jc = n2 R3 + j3, twiddle w_n^(jc k1);
+//   stage B1  DFT_R2 over n2 for each (k1, j3), twiddle w_(R2 R3)^(j3 k2);
+//   stage B2  DFT_R3 over j3 for each (k1, k2);
+// giving wave number k = k1 + R1 (k2 + R2 k3).  The kinetic phase is applied
+// there, and the transposed network (conjugate twiddles, inverse DFTs in the
+// reverse order) brings every thread back to the elements it loaded.  Between
+// stages the line is exchanged through LDS, each stage reading and writing its
+// own disjoint set of positions.
+#pragma once
+
+#include "axis_pass.hpp"
+
+namespace hom4d_impl {
+namespace dev {
+
+template <int R1, int R2, int R3, int T>
+struct Net3 {
+    static constexpr int N = R1 * R2 * R3, N2 = R2 * R3;
+    static constexpr int JA = N2 / T;        // stage-A columns per thread
+    static constexpr int G1 = R1 * R3 / T;   // stage-B1 groups per thread
+    static constexpr int G2 = R1 * R2 / T;   // stage-B2 groups per thread
+    static constexpr int E = JA * R1;        // elements per thread
+    static_assert(N2 % T == 0 && (R1 * R3) % T == 0 && (R1 * R2) % T == 0, "T must split every stage");
+    static_assert(G1 * R2 == E && G2 * R3 == E, "every stage must give a thread E elements");
+};
+
+template <class S, int AXIS, int R1, int R2, int R3, int T, int VK>
+__global__ void __launch_bounds__(256) k_axis3(const PassArgs a) {
+    using NT = Net3<R1, R2, R3, T>;
+    constexpr int N = NT::N, N2 = NT::N2, JA = NT::JA, G1 = NT::G1, G2 = NT::G2, E = NT::E;
+    extern __shared__ double2 lds[];
+
+    const int W = a.W;
+    const int tid = threadIdx.x;
+    int t, cl;
+    if constexpr (AXIS == AX_Y2) {
+        t = tid % T;
+        cl = tid / T;
+    } else {
+        cl = tid % W;
+        t = tid / W;
+    }
+    const uint32_t line = blockIdx.x * (uint32_t)W + (uint32_t)cl;
+    const LineGeom<AXIS> lg(a, line);
+
+    // twiddles w_n^j (and, on y axes, the kinetic factor) staged after the exchange area
+    constexpr bool KT_LDS = (AXIS == AX_Y1 || AXIS == AX_Y2);
+    const int LS = W + 1;  // padded LDS row: one line position across the block's W lines
+    double2* twl = lds + N * LS;
+    for (int i = tid; i < (KT_LDS ? 2 * N : N); i += T * W) {
+        double2 w;
+        if (i < N) {
+            w = a.tw[i];
+        } else {
+            w = a.ktab[i - N];
+            if (a.kconj) w = conjd(w);
+        }
+        twl[i] = w;
+    }
+    __syncthreads();
+    auto L = [&](int pos) -> double2& { return lds[pos * LS + cl]; };
+
+    S* ps = reinterpret_cast<S*>(a.psi) + lg.base;
+    double2 v[E];
+#pragma unroll
+    for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) v[jj * R1 + n1] = ld<S>(ps + (int64_t)(n1 * N2 + t + T * jj) * lg.sN);
+
+    auto potential = [&]() {
+#pragma unroll
+        for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) {
+                int c[4];
+                elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, n1 * N2 + t + T * jj, c);
+                v[jj * R1 + n1] = cmul(v[jj * R1 + n1], vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]));
+            }
+    };
+    if (VK != 0 && a.vmode == 1) potential();
+
+    // ---- stage A (forward)
+#pragma unroll
+    for (int jj = 0; jj < JA; ++jj) {
+        const int jc = t + T * jj;
+        dft<R1, -1>(&v[jj * R1]);
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmul(v[jj * R1 + k1], twl[(jc * k1) % N]);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) L(k1 * N2 + jc) = v[jj * R1 + k1];
+    }
+    __syncthreads();
+
+    // ---- stage B1 (forward), in place on its positions
+#pragma unroll
+    for (int ii = 0; ii < G1; ++ii) {
+        const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) v[ii * R2 + n2] = L(k1 * N2 + n2 * R3 + j3);
+        dft<R2, -1>(&v[ii * R2]);
+#pragma unroll
+        for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmul(v[ii * R2 + k2], twl[(R1 * j3 * k2) % N]);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) L(k1 * N2 + k2 * R3 + j3) = v[ii * R2 + k2];
+    }
+    __syncthreads();
+
+    // ---- stage B2: forward, kinetic phase at k = k1 + R1 (k2 + R2 k3), inverse
+    // x kinetic factor table: y-major [y][k] on the x1 pass, k-major [k][y] on the x2 pass
+    const int yrow = (AXIS == AX_X1) ? lg.j1 : ((AXIS == AX_X2) ? lg.j2 : 0);
+    const double2* kt = a.ktab + (AXIS == AX_X1 ? (int64_t)yrow * N : (int64_t)yrow);
+    const int64_t kstride = AXIS == AX_X1 ? 1 : a.ny;
+#pragma unroll
+    for (int ii = 0; ii < G2; ++ii) {
+        const int q = t + T * ii, k1 = q / R2, k2 = q % R2;
+#pragma unroll
+        for (int j3 = 0; j3 < R3; ++j3) v[ii * R3 + j3] = L(k1 * N2 + k2 * R3 + j3);
+        dft<R3, -1>(&v[ii * R3]);
+#pragma unroll
+        for (int k3 = 0; k3 < R3; ++k3) {
+            const int k = k1 + R1 * (k2 + R2 * k3);
+            double2 f;
+            if constexpr (KT_LDS) {
+                f = twl[N + k];
+            } else {
+                f = kt[k * kstride];
+                if (a.kconj) f = conjd(f);
+            }
+            v[ii * R3 + k3] = cmul(v[ii * R3 + k3], f);
+        }
+        dft<R3, 1>(&v[ii * R3]);
+#pragma unroll
+        for (int j3 = 0; j3 < R3; ++j3) L(k1 * N2 + k2 * R3 + j3) = v[ii * R3 + j3];
+    }
+    __syncthreads();
+
+    // ---- stage B1 (inverse)
+#pragma unroll
+    for (int ii = 0; ii < G1; ++ii) {
+        const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[ii * R2 + k2] = L(k1 * N2 + k2 * R3 + j3);
+#pragma unroll
+        for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmulc(v[ii * R2 + k2], twl[(R1 * j3 * k2) % N]);
+        dft<R2, 1>(&v[ii * R2]);
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) L(k1 * N2 + n2 * R3 + j3) = v[ii * R2 + n2];
+    }
+    __syncthreads();
+
+    // ---- stage A (inverse), back on the loaded elements
+#pragma unroll
+    for (int jj = 0; jj < JA; ++jj) {
+        const int jc = t + T * jj;
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) v[jj * R1 + k1] = L(k1 * N2 + jc);
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmulc(v[jj * R1 + k1], twl[(jc * k1) % N]);
+        dft<R1, 1>(&v[jj * R1]);
+    }
+
+    if (VK != 0 && a.vmode == 2) potential();
+
+#pragma unroll
+    for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) st<S>(ps + (int64_t)(n1 * N2 + t + T * jj) * lg.sN, v[jj * R1 + n1]);
+}
+
+// Three-stage factorisations: n = R1 R2 R3 on T threads per line.
+template <class S, int AXIS, int VK>
+AxisKernel pick3(int n, int* t) {
+    switch (n) {
+        case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, VK>;
+        case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, VK>;
+        default: *t = 0; return nullptr;
+    }
+}
+
+// Forward single-state passes: the x1 pass carries no potential factor, the
+// y2 pass always carries it, x2 and y1 either.
+template <class S>
+AxisKernel pick_axis3(int axis, int n, int vk, int* t) {
+    switch (axis) {
+        case AX_X1:
+            if (vk == 0) return pick3<S, AX_X1, 0>(n, t);
+            break;
+        case AX_X2:
+            if (vk == 0) return pick3<S, AX_X2, 0>(n, t);
+            if (vk == 1) return pick3<S, AX_X2, 1>(n, t);
+            if (vk == 2) return pick3<S, AX_X2, 2>(n, t);
+            break;
+        case AX_Y1:
+            if (vk == 0) return pick3<S, AX_Y1, 0>(n, t);
+            if (vk == 1) return pick3<S, AX_Y1, 1>(n, t);
+            if (vk == 2) return pick3<S, AX_Y1, 2>(n, t);
+            break;
+        case AX_Y2:
+            if (vk == 1) return pick3<S, AX_Y2, 1>(n, t);
+            if (vk == 2) return pick3<S, AX_Y2, 2>(n, t);
+            break;
+        default: break;
+    }
+    *t = 0;
+    return nullptr;
+}
+
+}  // namespace dev
+}  // namespace hom4d_impl

@@ -114,6 +114,46 @@ __device__ __forceinline__ void elem_coord(int i1, int j1, int i2, int j2, int m
     c[AXIS] = m;
 }
 
+// Position of line number `line` of a pass along AXIS in the [x1][y1][x2][y2]
+// state: its fixed coordinates (the one along AXIS is left 0), the offset of its
+// first element and the element stride.  Lines are numbered so that
+// consecutive lines are adjacent in memory on the strided axes.
+template <int AXIS>
+struct LineGeom {
+    int i1 = 0, j1 = 0, i2 = 0, j2 = 0;
+    int64_t base, sN;
+    __device__ __forceinline__ LineGeom(const PassArgs& a, uint32_t line) {
+        const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nxy = nx * ny;
+        if constexpr (AXIS == AX_X1) {
+            j1 = (int)(line / nxy);
+            i2 = (int)((line / ny) % nx);
+            j2 = (int)(line % ny);
+            base = line;
+            sN = (int64_t)ny * nxy;
+        } else if constexpr (AXIS == AX_Y1) {
+            i1 = (int)(line / nxy);
+            const uint32_t c = line % nxy;
+            i2 = (int)(c / ny);
+            j2 = (int)(c % ny);
+            base = (int64_t)i1 * ny * nxy + c;
+            sN = nxy;
+        } else if constexpr (AXIS == AX_X2) {
+            const uint32_t o = line / ny;
+            i1 = (int)(o / ny);
+            j1 = (int)(o % ny);
+            j2 = (int)(line % ny);
+            base = (int64_t)o * nxy + j2;
+            sN = ny;
+        } else {
+            i1 = (int)(line / nxy);
+            j1 = (int)((line / nx) % ny);
+            i2 = (int)(line % nx);
+            base = (int64_t)line * ny;
+            sN = 1;
+        }
+    }
+};
+
 // VK: 0 = no potential factor on this pass, 1 = table form, 2 = per-point form.
 template <class S, int AXIS, int N1, int N2, int T, int NST, int VK>
 __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
@@ -135,36 +175,9 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         t = tid / W;
     }
     const uint32_t line = blockIdx.x * (uint32_t)W + (uint32_t)cl;
-    const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nxy = nx * ny;
-    int i1 = 0, j1 = 0, i2 = 0, j2 = 0;
-    int64_t base, sN;
-    if constexpr (AXIS == AX_X1) {
-        j1 = (int)(line / nxy);
-        i2 = (int)((line / ny) % nx);
-        j2 = (int)(line % ny);
-        base = line;
-        sN = (int64_t)ny * nxy;
-    } else if constexpr (AXIS == AX_Y1) {
-        i1 = (int)(line / nxy);
-        const uint32_t c = line % nxy;
-        i2 = (int)(c / ny);
-        j2 = (int)(c % ny);
-        base = (int64_t)i1 * ny * nxy + c;
-        sN = nxy;
-    } else if constexpr (AXIS == AX_X2) {
-        const uint32_t o = line / ny;
-        i1 = (int)(o / ny);
-        j1 = (int)(o % ny);
-        j2 = (int)(line % ny);
-        base = (int64_t)o * nxy + j2;
-        sN = ny;
-    } else {
-        i1 = (int)(line / nxy);
-        j1 = (int)((line / nx) % ny);
-        i2 = (int)(line % nx);
-        base = (int64_t)line * ny;
-        sN = 1;
-    }
+    const LineGeom<AXIS> lg(a, line);
+    const int i1 = lg.i1, j1 = lg.j1, i2 = lg.i2, j2 = lg.j2;
+    const int64_t base = lg.base, sN = lg.sN;
 
     // twiddles (and, on y axes, the kinetic factor) staged in LDS after the exchange area
     constexpr bool KT_LDS = (AXIS == AX_Y1 || AXIS == AX_Y2);

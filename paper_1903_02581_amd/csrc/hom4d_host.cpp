@@ -126,6 +126,20 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
     p.t = sh.t;
     const int64_t nxy = (int64_t)nx * ny;
     p.nlines = nxy * nxy / p.n;
+    const int t3 = axis3_threads(p.n, nst);
+    if (t3 > 0) {
+        // three-stage kernel: exchange area of n (W + 1) entries plus 2n staged
+        // factors within 48 KB, so that three or more blocks share a CU
+        p.t = t3;
+        int64_t w = 256 / t3;
+        const int64_t cap = (49152 - 2 * p.n * 16) / ((int64_t)p.n * 16) - 1;
+        while (w > cap) w >>= 1;
+        w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
+        if (axis == AX_X2) w = std::min<int64_t>(w, ilog2_pow2_divisor(ny));
+        p.W = (int)std::max<int64_t>(w, 1);
+        p.lds = ((size_t)p.n * (p.W + 1) + 2 * (size_t)p.n) * sizeof(double2);
+        return p;
+    }
     int64_t w = 256 / sh.t;
     if (sh.n2 > 1) {
         // LDS per block: 64 KB for complex128 storage (W = 16 lines already gives

@@ -55,6 +55,11 @@ struct FftShape {
 // Supported line lengths and their register/LDS decomposition.
 bool fft_shape(int n, FftShape* out);
 
+// Threads per line of the three-stage pass kernel used for the forward
+// single-state passes of long lines (n = 96, 128); 0 where the two-stage
+// kernel runs.
+int axis3_threads(int n, int nst);
+
 // Launch one per-axis pass: blocks of t*W threads, nlines/W blocks.
 hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, int64_t nlines,
                        size_t lds_bytes, hipStream_t s);

@@ -34,6 +34,8 @@ AxisKernel pick_axis_f64_1(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f64_2(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f32_1(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f32_2(int axis, int n, int vk, int* t);
+AxisKernel pick_axis3_f64(int axis, int n, int vk, int* t);
+AxisKernel pick_axis3_f32(int axis, int n, int vk, int* t);
 AxisKernel pick_plane_f64(int nx, int ny, int vk, int* nt);
 AxisKernel pick_plane_f32(int nx, int ny, int vk, int* nt);
 
@@ -204,6 +206,15 @@ inline int obs_threads() { return 256; }
 
 }  // namespace
 
+int axis3_threads(int n, int nst) {
+    if (nst != 1) return 0;
+    switch (n) {
+        case 96: return 8;
+        case 128: return 16;
+        default: return 0;
+    }
+}
+
 bool fft_shape(int n, FftShape* out) {
     switch (n) {
         case 4: *out = {4, 1, 1}; return true;
@@ -227,7 +238,9 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
     int t = 0;
     AxisKernel fn = nullptr;
     const int vk = a.vmode == 0 ? 0 : (a.vdirect ? 2 : 1);
-    if (!mixed)
+    if (axis3_threads(n, nst) > 0)
+        fn = mixed ? pick_axis3_f32(axis, n, vk, &t) : pick_axis3_f64(axis, n, vk, &t);
+    else if (!mixed)
         fn = (nst == 2) ? pick_axis_f64_2(axis, n, vk, &t) : pick_axis_f64_1(axis, n, vk, &t);
     else
         fn = (nst == 2) ? pick_axis_f32_2(axis, n, vk, &t) : pick_axis_f32_1(axis, n, vk, &t);
