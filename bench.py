@@ -6,9 +6,10 @@ points (268 MB), box 800 x 600 nm, GaAs (m* = 0.067, eps_r = 12.9), B = 5 T,
 dt = 2 fs, 2000 Strang steps, softened Coulomb (d = 2 nm), saddle QPC with
 the first (V0, sigma_x) of the seeded 9-run sweep.  Synthetic, seeded inputs.
 
-A step is one Strang step S(dt) of the whole hot path: two x passes, the y1
-pass with the potential factor, the y2 pass with the potential factor
-(Sec. II.C Eq. (evoloperat) of arXiv 1903.02581), with the region
+A step is one Strang step S(dt) of the whole hot path (Sec. II.C Eq.
+(evoloperat) of arXiv 1903.02581): the x1 pass, the fused pass over each
+(x2, y2) plane (x2 transform and kinetic phase, potential factor, y2 transform
+and kinetic phase), and the y1 pass with the potential factor, with the region
 probabilities (Eq. (p_bunching)) sampled every 100 steps inside the timed
 region.  value = grid-point-steps per second = (nx ny)^2 * steps / time.
 
@@ -37,8 +38,21 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 AXES = {0: "x1", 1: "y1", 2: "x2+V", 3: "y2+V", 4: "plane(x2,V,y2)", 5: "y1+V"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mid.json")
+# what decides the code and launch shape of the timed pass kernels: the kernel
+# headers whole, and the launch-planning functions of the host and launch sources
 KERNEL_SOURCES = ["paper_1903_02581_amd/csrc/axis_pass.hpp", "paper_1903_02581_amd/csrc/dft_regs.hpp",
-                  "paper_1903_02581_amd/csrc/plane_pass.hpp", "paper_1903_02581_amd/csrc/hom4d_host.cpp"]
+                  "paper_1903_02581_amd/csrc/plane_pass.hpp", "paper_1903_02581_amd/csrc/hom4d_internal.hpp"]
+KERNEL_FUNCTIONS = [("paper_1903_02581_amd/csrc/hom4d_host.cpp", "AxisPlan plan_axis("),
+                    ("paper_1903_02581_amd/csrc/hom4d_kernels.hip", "hipError_t launch_axis("),
+                    ("paper_1903_02581_amd/csrc/hom4d_kernels.hip", "hipError_t launch_plane(")]
+
+
+def _function_text(path: str, head: str) -> bytes:
+    with open(os.path.join(ROOT, path)) as f:
+        text = f.read()
+    i = text.index(head)
+    j = text.index("\n}\n", i)
+    return text[i:j + 3].encode()
 
 
 def kernel_hash() -> str:
@@ -46,6 +60,8 @@ def kernel_hash() -> str:
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    for p, head in KERNEL_FUNCTIONS:
+        h.update(_function_text(p, head))
     return h.hexdigest()[:16]
 
 

@@ -7,7 +7,8 @@ region probabilities at full size from 2D runs (orbital_observables).  The
 GPU path (four per-axis passes per step at this size) must match them, and the
 sigma sweep reproduces the qualitative result of Sec. III.A: bunching of the
 Slater determinant decreases with the packet length, while distinguishable
-electrons bunch with probability 1/2 at a balanced splitter.  The 1D model of
+electrons bunch with probability 1/2 at a balanced splitter, and displacing one
+packet along its edge brings the bunching back towards 1/2.  The 1D model of
 Sec. III.A Eq. (bunching) at zero displacement, P_b = (1 - sigma^2/Sigma^2)/2
 with Sigma^2 = sigma^2 + a^2/(8 gamma), gives one QPC length a per sigma."""
 import numpy as np
@@ -83,3 +84,19 @@ def test_coulomb_mixed_against_fp64():
     ref0 = O.orbital_observables(a, b, w0.w_top, -1)
     announce(f"qpc sigma=15: P_b Coulomb {o64['p_b']:.6f} (mixed {o32['p_b']:.6f}), "
              f"exchange only {ref0['p_b']:.6f}")
+
+
+def test_displaced_packets_recover_half():
+    # a displacement between the packets along their edges reduces their overlap at the
+    # splitter, and with it the exchange antibunching (Sec. III.B, the displacement axis)
+    pb = {}
+    for shift in (0.0, 40.0):
+        w = preset("qpc", shift_nm=shift, steps=3200)
+        announce(f"qpc 128x64 fp64 shift={shift} nm steps={w.steps} V12=0 antisym")
+        o = _gpu_obs(w)
+        a, b = _orbitals(w)
+        ref = O.orbital_observables(a, b, w.w_top, -1)
+        assert abs(o["p_b"] - ref["p_b"]) <= 1e-10
+        announce(f"qpc shift={shift}: P_b={o['p_b']:.10f} (oracle {ref['p_b']:.10f})")
+        pb[shift] = o["p_b"]
+    assert pb[40.0] > pb[0.0] + 0.03

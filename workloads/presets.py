@@ -188,15 +188,17 @@ def build(name: str, nx: int, ny: int, lx: float, ly: float, *, b_tesla: float,
           sy: float = 60.0, sigma_x: float = 20.0, seed: int = 0,
           mstar_rel: float = 0.067, eps_r: float = 12.9, ckpt_every: int = 100,
           e_above_lll: float = 2.0, qpc_gap_nm: float | None = None,
-          qpc_half_nm: float = 15.0) -> Workload:
+          qpc_half_nm: float = 15.0, shift_nm: float = 0.0) -> Workload:
     """qpc_gap_nm set: the beam splitter is the Fermi-block constriction
-    (fermi_block_qpc) instead of the saddle, and v0, v1, sx, sy are unused."""
+    (fermi_block_qpc) instead of the saddle, and v0, v1, sx, sy are unused.
+    shift_nm moves the bottom packet's start away from the splitter along its
+    edge (the displacement between the two packets of Sec. III.B)."""
     x = grid_x(nx, lx)
     y = grid_x(ny, ly)
     dx = lx / nx
     jit = np.random.default_rng(seed).uniform(-0.5 * dx, 0.5 * dx, 2)
     xa = -0.25 * lx + jit[0]
-    xb = +0.25 * lx + jit[1]
+    xb = +0.25 * lx + shift_nm + jit[1]
     if qpc_gap_nm is None:
         v = saddle_potential(x, y, v0, v1, sx, sy, ly)
     else:
@@ -215,7 +217,7 @@ def build(name: str, nx: int, ny: int, lx: float, ly: float, *, b_tesla: float,
                     sigma_x=sigma_x, seed=seed, v_table=v, psi_a=psi_a, psi_b=psi_b,
                     w_top=top_weights(nx, ny, ly), ckpt_every=ckpt_every,
                     info=dict(xa=xa, xb=xb, alpha=ia_info, beta=ib_info, qpc_gap_nm=qpc_gap_nm,
-                              qpc_half_nm=qpc_half_nm))
+                              qpc_half_nm=qpc_half_nm, shift_nm=shift_nm))
 
 
 def mid_sweep():
@@ -273,8 +275,8 @@ def _qpc(seed=0, **kw):
     kw.setdefault("qpc_gap_nm", QPC_GAP_NM)
     kw.setdefault("e_above_lll", 5.0)
     kw.setdefault("coulomb_c", 0.0)
-    return build("qpc", 128, 64, 400.0, 256.0, b_tesla=5.0, dt_fs=1.0, steps=2500,
-                 soft_nm=1.0, seed=seed, **kw)
+    kw.setdefault("steps", 2500)
+    return build("qpc", 128, 64, 400.0, 256.0, b_tesla=5.0, dt_fs=1.0, soft_nm=1.0, seed=seed, **kw)
 
 
 PRESETS = {"tiny": _tiny, "mid": _mid, "mixed": _mixed, "diff": _diff, "full": _full,
