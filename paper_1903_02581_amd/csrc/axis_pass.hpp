@@ -53,12 +53,14 @@ __device__ __forceinline__ double reduce_2pi(double th) {
 
 // exp(-i tau (V(r1) + V(r2) + V12(r1 - r2)) / hbar), or its conjugate.
 // VK = 1: product of the one-body and two-body factor tables; VK = 2: the FP64
-// angle evaluated here, reduced mod 2 pi, then sincos.
+// angle evaluated here, reduced mod 2 pi, then sincos; VK = 3: as VK = 1
+// without the one-body factor of electron 1 (applied by the caller).
 template <int VK>
 __device__ __forceinline__ double2 vfactor(const PassArgs& a, int i1, int j1, int i2, int j2) {
     double2 f;
-    if constexpr (VK == 1) {
-        f = cmul(a.a1[i1 * a.ny + j1], a.a1[i2 * a.ny + j2]);
+    if constexpr (VK == 1 || VK == 3) {
+        f = a.a1[i2 * a.ny + j2];
+        if constexpr (VK == 1) f = cmul(a.a1[i1 * a.ny + j1], f);
         if (a.ac) f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)]);
         if (a.kconj) f = conjd(f);
     } else {
@@ -315,7 +317,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         for (int s = 0; s < NST; ++s)
 #pragma unroll
             for (int ii = 0; ii < IB; ++ii) dft<N2, 1>(&v[s][ii * N2]);
-        __syncthreads();
+        // each thread writes back exactly the positions it read for stage B: no barrier needed
 #pragma unroll
         for (int s = 0; s < NST; ++s)
 #pragma unroll

@@ -41,7 +41,9 @@ struct PlaneLds {
     __device__ static __forceinline__ int at(int r, int p) { return r * row + p + (p >> 3); }
 };
 
-// One plane per workgroup, grid = nx * ny.
+// One plane per workgroup, grid = nx * ny.  Barriers: one after every LDS write
+// that other threads read back; none before a write, because each exchange
+// writes exactly the positions the same thread read in the previous one.
 template <class S, int NX, int NY, int NT, int VK>
 __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     using SX_ = Shape<NX>;
@@ -58,12 +60,18 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     __shared__ double2 TW[NX + 2 * NY];  // x twiddles, y twiddles, y kinetic factor
 
     const int tid = threadIdx.x;
+    const int r1 = blockIdx.x;
+    const int i1 = r1 / NY, j1 = r1 % NY;
+    // The one-body factor of electron 1 is one number for the whole plane, so it
+    // is folded into the y kinetic factor here instead of multiplying each point.
+    const double2 v1 = (VK == 1) ? a.a1[r1] : make_double2(1.0, 0.0);
     for (int i = tid; i < NX + 2 * NY; i += NT) {
         double2 v;
         if (i < NX) v = a.tw[i];
         else if (i < NX + NY) v = a.tw2[i - NX];
         else {
             v = a.ktab2[i - NX - NY];
+            if constexpr (VK == 1) v = cmul(v, v1);
             if (a.kconj) v = conjd(v);
         }
         TW[i] = v;
@@ -77,8 +85,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
         return s < SLX;
     };
 
-    const int r1 = blockIdx.x;
-    const int i1 = r1 / NY, j1 = r1 % NY;
     S* base = reinterpret_cast<S*>(a.psi) + (int64_t)r1 * (NX * NY);
     double2 vx[QX][EX];
 #pragma unroll
@@ -168,7 +174,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
             }
         }
         if constexpr (A2 > 1) {
-            __syncthreads();
 #pragma unroll
             for (int q = 0; q < QX; ++q) {
                 int c, t;
@@ -210,12 +215,11 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                 for (int jj = 0; jj < JAX; ++jj)
 #pragma unroll
                     for (int n1 = 0; n1 < A1; ++n1) {
-                        const double2 f = vfactor<VK>(av, i1, j1, n1 * A2 + t + TX * jj, c);
+                        const double2 f = vfactor<VK == 1 ? 3 : VK>(av, i1, j1, n1 * A2 + t + TX * jj, c);
                         vb[q][jj * A1 + n1] = cmul(vb[q][jj * A1 + n1], f);
                     }
             }
         }
-        __syncthreads();  // every X2-stage read of L is done
 #pragma unroll
         for (int q = 0; q < QX; ++q) {
             int c, t;
@@ -252,7 +256,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
             }
         }
         if constexpr (B2 > 1) {
-            __syncthreads();
 #pragma unroll
             for (int q = 0; q < QY; ++q) {
                 const int s = tid + NT * q;
@@ -297,7 +300,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
             }
         }
         if constexpr (B2 > 1) {
-            __syncthreads();
 #pragma unroll
             for (int q = 0; q < QY; ++q) {
                 const int s = tid + NT * q;
