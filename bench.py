@@ -15,7 +15,8 @@ region.  value = grid-point-steps per second = (nx ny)^2 * steps / time.
 
 Extra objects on the JSON line:
   roofline     -- the dominant pass kernel, timed with HIP events on the
-                  library's stream, against the 8 TB/s HBM peak;
+                  library's stream, against the 8 TB/s HBM peak (and, for
+                  context, against a measured 1 GiB device copy);
   cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same workload;
   mixed        -- the complex64-storage form on the same workload and its error
                   against the FP64 GPU run (|dP_b|, relative L2 of psi, norm).
@@ -110,6 +111,32 @@ def pass_timing(prop, reps=50):
         end.synchronize()
         out[AXES[axis]] = start.elapsed_time(end) / reps * 1e-3   # seconds per launch
     return out
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes per second) of a buffer far
+    larger than the caches: the achievable-HBM reference for the roofline."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    end.record()
+    end.synchronize()
+    gbs = 2 * nbytes * reps / (start.elapsed_time(end) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def describe(w):
+    return (f"{w.name}: {w.nx}x{w.ny} grid per electron ({w.points} points), {w.lx:g}x{w.ly:g} nm, "
+            f"GaAs, B={w.b_tesla:g}T, dt={w.dt_fs:g}fs, "
+            + (f"softened Coulomb d={w.soft_nm:g}nm" if w.coulomb_c else "no Coulomb term"))
 
 
 def cpu_baseline(w, budget_s):
@@ -255,6 +282,7 @@ def main():
     achieved = alg_bytes / passes[dom] / 1e9
     traffic = read_traffic(alg_bytes)
     prop.close()
+    copy_gbs = copy_bandwidth()
 
     mixed = None
     if args.precision == "fp64" and not args.no_mixed:
@@ -314,8 +342,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "c64-storage/f64",
         "data": "synthetic",
-        "config": {"workload": "mid: 64x64 grid per electron (16.8M complex128 points), 800x600 nm, "
-                               "GaAs, B=5T, dt=2fs, softened Coulomb d=2nm, sweep run 0",
+        "config": {"workload": describe(w) + (", sweep run 0" if w.name == "mid" else ""),
                    "nx": w.nx, "ny": w.ny, "points": P, "precision": args.precision,
                    "observables_every": args.sample_every, "passes_per_step": passes_per_step,
                    "final_p_b": obs64["p_b"],
@@ -324,7 +351,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (traffic["bytes_per_launch"][dom] if traffic else None),
                      "kernel": f"pass kernel {dom}", "algorithmic_bytes_per_launch": alg_bytes,
-                     "avg_launch_s": passes[dom], "pass_seconds": passes},
+                     "avg_launch_s": passes[dom], "pass_seconds": passes,
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "cpu_baseline": cpu,
         "mixed": mixed,
         "extras": extras,

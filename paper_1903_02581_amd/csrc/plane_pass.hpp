@@ -31,14 +31,18 @@ template <> struct Shape<64> { static constexpr int n1 = 8, n2 = 8, t = 8; };
 template <> struct Shape<96> { static constexpr int n1 = 12, n2 = 8, t = 4; };
 template <> struct Shape<128> { static constexpr int n1 = 16, n2 = 8, t = 8; };
 
-// LDS row layout of the plane: element p of row r at r * PLANE_LDP + p + p / 8.
-// The skew of one slot per 8 elements keeps both the row-wise (stride-1 across
-// lanes) and the sub-row (stride-8 within a thread) accesses of the y stage
-// free of bank conflicts; columns (the x stage) are stride-1 across lanes.
+// LDS row layout of the plane: element p of row r at r * row + (p ^ ((p / 8) % 8)),
+// row = NY + NY / 8.  The XOR permutes each aligned group of 8 slots, so the
+// image stays in bounds.  For 16-byte accesses, 16 consecutive lanes must hit
+// 16 different 16-byte bank groups: the x stage (lanes along a row, stride 1),
+// the y stage's row reads (8 lanes along each of two rows) and its sub-row
+// reads (stride 8 along two rows) all do at 64 x 64, where row = 72 puts the
+// two rows of a lane group half a bank cycle apart.
 template <int NY>
 struct PlaneLds {
-    static constexpr int row = NY + (NY + 7) / 8;
-    __device__ static __forceinline__ int at(int r, int p) { return r * row + p + (p >> 3); }
+    static_assert(NY % 8 == 0, "plane rows are whole groups of 8");
+    static constexpr int row = NY + NY / 8;
+    __device__ static __forceinline__ int at(int r, int p) { return r * row + (p ^ ((p >> 3) & 7)); }
 };
 
 // One plane per workgroup, grid = nx * ny.  Barriers: one after every LDS write
