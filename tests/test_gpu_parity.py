@@ -9,7 +9,7 @@ import pytest
 import oracle as O
 from workloads import preset
 from workloads.presets import build
-from tests.gpu_util import announce, gpu_run, oracle_run, rel_l2
+from tests.gpu_util import announce, gpu_run, grid_of, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -204,3 +204,20 @@ def test_marginal_and_conditional_densities():
             # Pauli node at r1 = r2*: exact zero up to the storage rounding
             assert c[ix2, jy2] <= (1e-20 if prec == "fp64" else 1e-9) * c.max()
         p.close()
+
+
+def test_zero_field_and_identical_orbitals():
+    # B = 0: the x kinetic factor loses its y dependence (free motion along x)
+    w = preset("tiny", b_tesla=0.0)
+    announce("tiny fp64 B=0 steps=50")
+    psi, _ = gpu_run(w, 50)
+    ref, _ = oracle_run(w, 50)
+    assert rel_l2(psi, ref) <= FP64_TOL
+    # the symmetric state of two identical orbitals (a doubly occupied orbital)
+    announce("tiny fp64 identical orbitals sym=+1 steps=50")
+    w2 = preset("tiny")
+    w2.psi_b = w2.psi_a.copy()
+    psi, obs = gpu_run(w2, 50, sym=1)
+    ref = O.propagate(O.init_state(w2.psi_a, w2.psi_a, 1), grid_of(w2), w2.v_table, w2.dt_fs, 50)
+    assert rel_l2(psi, ref) <= FP64_TOL
+    assert abs(obs["p_tb"] - obs["p_bt"]) <= 1e-12

@@ -226,37 +226,43 @@ def mid_sweep():
     return [(float(v0s[r // 3]), (10.0, 20.0, 40.0)[r % 3]) for r in range(9)]
 
 
+def _with(kw, **defaults):
+    """Preset defaults, overridden by the caller's keywords."""
+    out = dict(defaults)
+    out.update(kw)
+    return out
+
+
 def _tiny(seed=0, **kw):
-    return build("tiny", 16, 16, 400.0, 400.0, b_tesla=5.0, dt_fs=5.0, steps=200,
-                 soft_nm=2.0, sigma_x=20.0, seed=seed, **kw)
+    return build("tiny", 16, 16, 400.0, 400.0, seed=seed,
+                 **_with(kw, b_tesla=5.0, dt_fs=5.0, steps=200, soft_nm=2.0, sigma_x=20.0))
 
 
 def _mid(seed=0, run=0, **kw):
     v0, sig = mid_sweep()[run]
-    kw.setdefault("v0", v0)
-    kw.setdefault("sigma_x", sig)
-    return build("mid", 64, 64, 800.0, 600.0, b_tesla=5.0, dt_fs=2.0, steps=2000,
-                 soft_nm=2.0, seed=seed if seed else run, **kw)
+    return build("mid", 64, 64, 800.0, 600.0, seed=seed if seed else run,
+                 **_with(kw, v0=v0, sigma_x=sig, b_tesla=5.0, dt_fs=2.0, steps=2000, soft_nm=2.0))
 
 
 def _mixed(seed=0, **kw):
-    return build("mixed", 128, 96, 1600.0, 900.0, b_tesla=6.0, dt_fs=1.0, steps=5000,
-                 soft_nm=1.0, sigma_x=20.0, seed=seed, **kw)
+    return build("mixed", 128, 96, 1600.0, 900.0, seed=seed,
+                 **_with(kw, b_tesla=6.0, dt_fs=1.0, steps=5000, soft_nm=1.0, sigma_x=20.0))
 
 
 def _diff(seed=0, **kw):
-    return build("diff", 48, 48, 600.0, 450.0, b_tesla=5.0, dt_fs=2.0, steps=1000,
-                 soft_nm=2.0, sigma_x=20.0, seed=seed, ckpt_every=100, **kw)
+    return build("diff", 48, 48, 600.0, 450.0, seed=seed,
+                 **_with(kw, b_tesla=5.0, dt_fs=2.0, steps=1000, soft_nm=2.0, sigma_x=20.0,
+                         ckpt_every=100))
 
 
 def _full(seed=0, **kw):
-    return build("full", 256, 128, 2000.0, 1000.0, b_tesla=5.0, dt_fs=0.5, steps=20000,
-                 soft_nm=2.0, sigma_x=10.0, seed=seed, **kw)
+    return build("full", 256, 128, 2000.0, 1000.0, seed=seed,
+                 **_with(kw, b_tesla=5.0, dt_fs=0.5, steps=20000, soft_nm=2.0, sigma_x=10.0))
 
 
 def _fp64_128(seed=0, **kw):
-    return build("fp64_128", 128, 128, 1000.0, 1000.0, b_tesla=5.0, dt_fs=0.5, steps=1000,
-                 soft_nm=2.0, sigma_x=10.0, seed=seed, **kw)
+    return build("fp64_128", 128, 128, 1000.0, 1000.0, seed=seed,
+                 **_with(kw, b_tesla=5.0, dt_fs=0.5, steps=1000, soft_nm=2.0, sigma_x=10.0))
 
 
 # Resolving beam-splitter workload.  At 5 T (l_B = 11.47 nm) the grid keeps
@@ -271,12 +277,9 @@ QPC_GAP_NM = 60.2
 
 
 def _qpc(seed=0, **kw):
-    kw.setdefault("sigma_x", 15.0)
-    kw.setdefault("qpc_gap_nm", QPC_GAP_NM)
-    kw.setdefault("e_above_lll", 5.0)
-    kw.setdefault("coulomb_c", 0.0)
-    kw.setdefault("steps", 2500)
-    return build("qpc", 128, 64, 400.0, 256.0, b_tesla=5.0, dt_fs=1.0, soft_nm=1.0, seed=seed, **kw)
+    return build("qpc", 128, 64, 400.0, 256.0, seed=seed,
+                 **_with(kw, sigma_x=15.0, qpc_gap_nm=QPC_GAP_NM, e_above_lll=5.0, coulomb_c=0.0,
+                         steps=2500, b_tesla=5.0, dt_fs=1.0, soft_nm=1.0))
 
 
 PRESETS = {"tiny": _tiny, "mid": _mid, "mixed": _mixed, "diff": _diff, "full": _full,
