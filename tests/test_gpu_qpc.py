@@ -100,3 +100,19 @@ def test_displaced_packets_recover_half():
         announce(f"qpc shift={shift}: P_b={o['p_b']:.10f} (oracle {ref['p_b']:.10f})")
         pb[shift] = o["p_b"]
     assert pb[40.0] > pb[0.0] + 0.03
+
+
+def test_exchange_symmetry_orders_bunching():
+    # symmetric orbital state bunches above 1/2, the Slater determinant below,
+    # distinguishable electrons at 1/2 (Sec. III.A, the two symmetries of Fig. 4)
+    w = preset("qpc")
+    a, b = _orbitals(w)
+    pb = {}
+    for sym in (1, 0, -1):
+        announce(f"qpc 128x64 fp64 sym={sym} steps={w.steps}")
+        o = _gpu_obs(w, sym=sym)
+        ref = O.orbital_observables(a, b, w.w_top, sym)
+        assert abs(o["p_b"] - ref["p_b"]) <= 1e-10
+        pb[sym] = o["p_b"]
+    announce(f"qpc P_b symmetric {pb[1]:.6f} product {pb[0]:.6f} antisymmetric {pb[-1]:.6f}")
+    assert pb[1] > pb[0] + 0.1 and pb[0] > pb[-1] + 0.1
