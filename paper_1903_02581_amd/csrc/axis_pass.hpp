@@ -183,19 +183,38 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
 
     // twiddles (and, on y axes, the kinetic factor) staged in LDS after the exchange area
     constexpr bool KT_LDS = (AXIS == AX_Y1 || AXIS == AX_Y2);
+    // On the y1 pass the block's lines share x1, so the one-body factor of
+    // electron 1 along the line, exp(-i tau V(x1, y1) / hbar) for every y1, is one
+    // table row: staged after the kinetic factor instead of read per element.
+    constexpr bool A1_LDS = (AXIS == AX_Y1 && VK == 1);
     double2* TWL = lds + (N2 > 1 ? NST * N * (W + 1) : 0);
-    for (int i = tid; i < (KT_LDS ? 2 * N : N); i += T * W) {
+    const int a1_row = A1_LDS ? (int)((blockIdx.x * (uint32_t)W) / ((uint32_t)a.nx * (uint32_t)a.ny)) * a.ny : 0;
+    for (int i = tid; i < (KT_LDS ? 2 * N : N) + (A1_LDS ? N : 0); i += T * W) {
         double2 v;
         if (i < N) {
             v = a.tw[i];
-        } else {
+        } else if (i < 2 * N) {
             v = a.ktab[i - N];
             if (a.kconj) v = conjd(v);
+        } else {
+            v = a.a1[a1_row + i - 2 * N];
         }
         TWL[i] = v;
     }
     __syncthreads();
     const double2* twl = TWL;
+    // potential factor of element m of this line
+    auto pfactor = [&](int m) -> double2 {
+        if constexpr (A1_LDS) {
+            double2 f = cmul(twl[2 * N + m], a.a1[i2 * a.ny + j2]);
+            if (a.ac) f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (m - j2 + a.ny - 1)]);
+            return a.kconj ? conjd(f) : f;
+        } else {
+            int c[4];
+            elem_coord<AXIS>(i1, j1, i2, j2, m, c);
+            return vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
+        }
+    };
 
     S* ps[NST];
     ps[0] = reinterpret_cast<S*>(a.psi) + base;
@@ -227,9 +246,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         for (int jj = 0; jj < JA; ++jj) {
 #pragma unroll
             for (int n1 = 0; n1 < N1; ++n1) {
-                int c[4];
-                elem_coord<AXIS>(i1, j1, i2, j2, n1 * N2 + t + T * jj, c);
-                const double2 f = vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
+                const double2 f = pfactor(n1 * N2 + t + T * jj);
 #pragma unroll
                 for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = cmul(v[s][jj * N1 + n1], f);
             }
@@ -351,9 +368,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         for (int jj = 0; jj < JA; ++jj) {
 #pragma unroll
             for (int n1 = 0; n1 < N1; ++n1) {
-                int c[4];
-                elem_coord<AXIS>(i1, j1, i2, j2, n1 * N2 + t + T * jj, c);
-                const double2 f = vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
+                const double2 f = pfactor(n1 * N2 + t + T * jj);
 #pragma unroll
                 for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = cmul(v[s][jj * N1 + n1], f);
             }

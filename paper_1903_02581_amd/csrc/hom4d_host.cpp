@@ -145,19 +145,21 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         // LDS per block: 64 KB for complex128 storage (W = 16 lines already gives
         // 256-byte runs), 80 KB for complex64 (two blocks per CU, W = 32 on n = 128)
         const int64_t budget = mixed ? 81920 : 65536;
-        const int64_t cap = (budget - 2 * p.n * 16) / ((int64_t)nst * p.n * 16) - 1;
+        const int64_t cap = (budget - 3 * p.n * 16) / ((int64_t)nst * p.n * 16) - 1;
         while (w > cap) w >>= 1;
     }
     w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
     if (axis == AX_X2) w = std::min<int64_t>(w, ilog2_pow2_divisor(ny));
     if (axis == AX_Y2 && grad) w = std::min<int64_t>(w, ilog2_pow2_divisor(nx));
+    if (axis == AX_Y1) w = std::min<int64_t>(w, ilog2_pow2_divisor(nxy));  // a block's lines share x1
     if (w < 1) w = 1;
     p.W = (int)w;
-    // exchange area, then the staged twiddles / kinetic factor (2n entries); the
-    // dual-state reduction scratch reuses the start of the allocation at the end
+    // exchange area, then the staged twiddles, kinetic factor and (y1) one-body
+    // factor row (3n entries); the dual-state reduction scratch reuses the start
+    // of the allocation at the end
     const size_t ex = sh.n2 > 1 ? (size_t)nst * p.n * (p.W + 1) * sizeof(double2) : 0;
     const size_t red = nst == 2 ? (size_t)sh.t * p.W * sizeof(double) : 0;
-    p.lds = std::max(ex + (size_t)2 * p.n * sizeof(double2), red);
+    p.lds = std::max(ex + (size_t)3 * p.n * sizeof(double2), red);
     return p;
 }
 

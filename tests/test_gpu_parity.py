@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 from workloads import preset
-from workloads.presets import build
+from workloads.presets import build, replace
 from tests.gpu_util import announce, gpu_run, grid_of, oracle_run, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -215,9 +215,9 @@ def test_zero_field_and_identical_orbitals():
     assert rel_l2(psi, ref) <= FP64_TOL
     # the symmetric state of two identical orbitals (a doubly occupied orbital)
     announce("tiny fp64 identical orbitals sym=+1 steps=50")
-    w2 = preset("tiny")
+    w2 = replace(preset("tiny"), sym=1)
     w2.psi_b = w2.psi_a.copy()
-    psi, obs = gpu_run(w2, 50, sym=1)
+    psi, obs = gpu_run(w2, 50)
     ref = O.propagate(O.init_state(w2.psi_a, w2.psi_a, 1), grid_of(w2), w2.v_table, w2.dt_fs, 50)
     assert rel_l2(psi, ref) <= FP64_TOL
     assert abs(obs["p_tb"] - obs["p_bt"]) <= 1e-12
