@@ -1,21 +1,22 @@
-// Device kernels of the two-electron split-step propagator (gfx950, wave64).
+// Launchers of the pass kernels and the elementwise / reduction kernels of the
+// two-electron split-step propagator (gfx950, wave64).
 //
-// The hot kernel is k_axis: one batched 1D transform along one of the four
-// coordinates of Psi[x1][y1][x2][y2], fused with the diagonal phase of that
-// coordinate's kinetic term in reciprocal space (Appendix A of arXiv
-// 1903.02581: T_x diagonal in (k_x, y), T_y diagonal in k_y) and, on the y
-// passes, with the real-space potential factor exp(-i tau (V1+V2+V12)/hbar)
-// (Sec. II.C Eq. (evoloperat); Sec. III.B Eq. (coulomb)).
+// The pass kernels (axis_pass.hpp, axis3_pass.hpp, plane_pass.hpp) apply one
+// batched transform round trip along a coordinate of Psi[x1][y1][x2][y2] with
+// the diagonal kinetic phase of that coordinate in reciprocal space (Appendix A
+// of arXiv 1903.02581: T_x diagonal in (k_x, y), T_y diagonal in k_y), and on
+// the passes that carry it the real-space potential factor
+// exp(-i tau (V1 + V2 + V12) / hbar) (Sec. II.C Eq. (evoloperat); Sec. III.B
+// Eq. (coulomb)).  A thread loads its elements of a line straight from HBM
+// (for strided axes consecutive lanes read consecutive lines, so every row
+// access of a wavefront is one contiguous run), runs register DFTs, exchanges
+// through LDS between radix stages, applies the phase at known wave numbers and
+// runs the transposed network back to its own elements, which it stores in
+// place.  All arithmetic is FP64; the state is stored as complex128 or complex64.
 //
-// Each line of length n = n1 * n2 is handled by t threads.  A thread loads
-// its n/t elements straight from HBM (for strided axes consecutive lanes read
-// consecutive lines, so every row access of a wavefront is one contiguous
-// run), runs n2/t register DFTs of size n1, multiplies the inter-stage
-// twiddles, exchanges through LDS, runs n1/t register DFTs of size n2, and
-// then holds n/t reciprocal-space values with known wave numbers: the phase
-// is applied there and the inverse runs the same network backwards, ending on
-// the thread's original elements, which it stores in place.  All arithmetic is
-// FP64; the state is stored as complex128 or complex64.
+// This file also holds the launch logic (kernel choice per line length,
+// storage type, state count and potential-factor form) and the FP64
+// reductions, whose partial sums are combined in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
