@@ -116,3 +116,25 @@ def test_exchange_symmetry_orders_bunching():
         pb[sym] = o["p_b"]
     announce(f"qpc P_b symmetric {pb[1]:.6f} product {pb[0]:.6f} antisymmetric {pb[-1]:.6f}")
     assert pb[1] > pb[0] + 0.1 and pb[0] > pb[-1] + 0.1
+
+
+def test_screened_coulomb_between_bare_and_none():
+    # the screened repulsion of Sec. III.B Eq. (screenedCoulomb) (C = 1, sigma_c = 5 nm)
+    # is much weaker than the bare one at the electrons' separations, so its bunching
+    # stays closer to the exchange-only value than the bare Coulomb bunching does
+    from paper_1903_02581_amd import Propagator
+    pb = {}
+    for label, kw in (("none", dict(coulomb_c=0.0)), ("screened", dict(coulomb_c=1.0)),
+                      ("bare", dict(coulomb_c=1.0))):
+        w = preset("qpc", **kw)
+        announce(f"qpc 128x64 fp64 Coulomb {label} steps={w.steps}")
+        extra = dict(screen_nm=5.0) if label == "screened" else {}
+        p = Propagator.from_workload(w, **extra)
+        p.step(w.steps)
+        o = p.observables(w.w_top)
+        p.close()
+        assert abs(o["norm"] - 1.0) <= 1e-11
+        pb[label] = o["p_b"]
+    announce(f"qpc P_b bare {pb['bare']:.6f} screened {pb['screened']:.6f} none {pb['none']:.6f}")
+    assert pb["bare"] < pb["none"]
+    assert abs(pb["screened"] - pb["none"]) < 0.5 * abs(pb["bare"] - pb["none"])
