@@ -138,3 +138,36 @@ def test_screened_coulomb_between_bare_and_none():
     announce(f"qpc P_b bare {pb['bare']:.6f} screened {pb['screened']:.6f} none {pb['none']:.6f}")
     assert pb["bare"] < pb["none"]
     assert abs(pb["screened"] - pb["none"]) < 0.5 * abs(pb["bare"] - pb["none"])
+
+
+def test_time_resolved_entanglement():
+    # spatial entanglement of the slice phi(x1, x2) = Psi(x1, y1*, x2, y2*) (Sec. III.C)
+    # with y1*, y2* on the two incoming edges: zero for the incoming product-like state,
+    # created by the scattering (0 -> 0.16 here); without the two-body term the slice is
+    # built exactly from the two propagated orbitals
+    from paper_1903_02581_amd import Propagator
+    w = preset("qpc")
+    g = grid_of(w, coulomb_c=0.0)
+    j1 = int(np.argmax(np.abs(w.psi_a).max(axis=0)))    # row of the top packet
+    j2 = int(np.argmax(np.abs(w.psi_b).max(axis=0)))    # row of the bottom packet
+    ix = np.arange(w.nx)
+    p = Propagator.from_workload(w)
+    a, b = w.psi_a.copy(), w.psi_b.copy()
+    scale = np.sqrt(2.0 * (1.0 - abs(np.vdot(w.psi_a, w.psi_b)) ** 2))
+    done = 0
+    s_t = []
+    for t in (0, 1000, 2000, 2500):
+        if t > done:
+            p.step(t - done)
+            a = O.propagate_2d(a, g, w.v_table, w.dt_fs, t - done)
+            b = O.propagate_2d(b, g, w.v_table, w.dt_fs, t - done)
+            done = t
+        announce(f"qpc entanglement at step {t}")
+        s_gpu = p.entanglement(ix, j1, ix, j2)
+        phi = (np.outer(a[:, j1], b[:, j2]) - np.outer(b[:, j1], a[:, j2])) / scale
+        s_ref = O.entanglement(phi[:, None, :, None], ix, 0, ix, 0)
+        announce(f"qpc S(step {t}) = {s_gpu:.10f} (oracle {s_ref:.10f})")
+        assert abs(s_gpu - s_ref) <= 1e-9
+        s_t.append(s_gpu)
+    p.close()
+    assert s_t[0] < 1e-6 and s_t[-1] > 0.1
