@@ -171,3 +171,18 @@ def test_time_resolved_entanglement():
         s_t.append(s_gpu)
     p.close()
     assert s_t[0] < 1e-6 and s_t[-1] > 0.1
+
+
+def test_coulomb_softening_sweep_distinguishable():
+    # distinguishable electrons with the softened repulsion (Sec. III.B): strong at a thin
+    # 2DEG (d = 1 nm), pushing P_b away from 1/2; a thick one (d = 100 nm) barely couples
+    # them and P_b returns towards 1/2
+    pb = {}
+    for d in (1.0, 100.0):
+        w = preset("qpc", coulomb_c=1.0, soft_nm=d, sym=0)
+        announce(f"qpc 128x64 fp64 product state d={d} nm steps={w.steps}")
+        o = _gpu_obs(w)
+        assert abs(o["norm"] - 1.0) <= 1e-11
+        pb[d] = o["p_b"]
+    announce(f"qpc product state P_b d=1: {pb[1.0]:.6f}, d=100: {pb[100.0]:.6f}")
+    assert abs(pb[100.0] - 0.5) < abs(pb[1.0] - 0.5)
