@@ -1,11 +1,11 @@
-// Per-axis pass for the long lines (n = 96, 128) of the forward step:
+// Per-axis pass for the long lines (n = 96, 128, 256) of the forward step:
 // the same transform -> kinetic phase -> inverse round trip as k_axis
 // (Sec. II.C Eq. (evoloperat); kinetic terms of Appendix A), with the line
 // transform factored into three radix stages instead of two, so that every
 // thread holds 8 (or 12) elements instead of 16 (or 24) and the kernels keep
-// enough waves resident to stream HBM.  (For n = 256 the three-stage form
-// needs 32 threads per line, which leaves too few lines per block for wide
-// HBM runs on the strided axes; the two-stage kernel stays faster there.)
+// enough waves resident to stream HBM.  n = 256 takes 32 threads per line, so
+// its blocks hold 16 lines in 512 threads (128-byte runs on the strided axes
+// in complex64 storage).
 //
 // Line of n = R1 R2 R3 points, element m = n1 (R2 R3) + n2 R3 + j3, handled by T
 // threads.  Forward:
@@ -36,7 +36,7 @@ struct Net3 {
 };
 
 template <class S, int AXIS, int R1, int R2, int R3, int T, int VK>
-__global__ void __launch_bounds__(256) k_axis3(const PassArgs a) {
+__global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     using NT = Net3<R1, R2, R3, T>;
     constexpr int N = NT::N, N2 = NT::N2, JA = NT::JA, G1 = NT::G1, G2 = NT::G2, E = NT::E;
     extern __shared__ double2 lds[];
@@ -184,6 +184,7 @@ AxisKernel pick3(int n, int* t) {
     switch (n) {
         case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, VK>;
         case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, VK>;
+        case 256: *t = 32; return k_axis3<S, AXIS, 8, 8, 4, 32, VK>;
         default: *t = 0; return nullptr;
     }
 }

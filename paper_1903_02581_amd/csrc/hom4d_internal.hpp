@@ -56,7 +56,7 @@ struct FftShape {
 bool fft_shape(int n, FftShape* out);
 
 // Threads per line of the three-stage pass kernel used for the forward
-// single-state passes of long lines (n = 96, 128); 0 where the two-stage
+// single-state passes of long lines (n = 96, 128, 256); 0 where the two-stage
 // kernel runs.
 int axis3_threads(int n, int nst);
 

@@ -212,6 +212,7 @@ int axis3_threads(int n, int nst) {
     switch (n) {
         case 96: return 8;
         case 128: return 16;
+        case 256: return 32;
         default: return 0;
     }
 }
@@ -247,7 +248,8 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
         fn = (nst == 2) ? pick_axis_f32_2(axis, n, vk, &t) : pick_axis_f32_1(axis, n, vk, &t);
     if (!fn || a.W <= 0 || nlines % a.W != 0) return hipErrorInvalidValue;
     const int64_t nblocks = nlines / a.W;
-    if (nblocks > 0x7fffffff || t * a.W > 256 || lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    const int max_threads = axis3_threads(n, nst) > 0 ? 512 : 256;
+    if (nblocks > 0x7fffffff || t * a.W > max_threads || lds_bytes > 160 * 1024) return hipErrorInvalidValue;
     if (lds_bytes > 64 * 1024) {
         // dynamic LDS above 64 KB has to be enabled per kernel, once
         static std::mutex mu;
