@@ -129,10 +129,11 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
     const int t3 = axis3_threads(p.n, nst);
     if (t3 > 0) {
         // three-stage kernel: exchange area of n (W + 1) entries plus 2n staged
-        // factors within 48 KB, so that three or more blocks share a CU; n = 256
-        // (32 threads per line) takes 16 lines in 512 threads and 80 KB
+        // factors.  n = 128: 16 lines (256 threads) within 48 KB, so that three
+        // or more blocks share a CU; n = 96 and 256 measured faster with wider
+        // blocks: 32 lines (256 threads) and 16 lines (512 threads) within 80 KB
         p.t = t3;
-        const bool wide = p.n >= 256;   // 16 lines (512 threads), 80 KB
+        const bool wide = p.n != 128;
         int64_t w = (wide ? 512 : 256) / t3;
         const int64_t cap = ((wide ? 81920 : 49152) - 2 * p.n * 16) / ((int64_t)p.n * 16) - 1;
         while (w > cap) w >>= 1;
