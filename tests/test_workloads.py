@@ -1,0 +1,73 @@
+"""The seeded input generators that feed both the oracle and the GPU path:
+the same seed gives the same arrays bit for bit, a different seed moves only the
+packet starts (the jitter of at most half a grid cell), and every preset hands
+over normalised orbitals, a finite potential table and region weights in
+{0, 1/2, 1}."""
+import numpy as np
+import pytest
+
+from workloads import preset
+from workloads.presets import PRESETS, mid_sweep
+
+CHEAP = ["tiny", "mid", "diff", "qpc", "mixed"]
+
+
+def _arrays(w):
+    return dict(v_table=w.v_table, psi_a=w.psi_a, psi_b=w.psi_b, w_top=w.w_top)
+
+
+@pytest.mark.parametrize("name", CHEAP)
+def test_same_seed_same_bits(name):
+    a, b = preset(name, seed=3), preset(name, seed=3)
+    for k, x in _arrays(a).items():
+        y = _arrays(b)[k]
+        assert x.dtype == y.dtype and x.shape == y.shape
+        assert x.tobytes() == y.tobytes(), (name, k)
+    assert a.cfg() == b.cfg() and a.info == b.info
+
+
+@pytest.mark.parametrize("name", ["tiny", "qpc"])
+def test_seed_moves_only_the_packet_starts(name):
+    a, b = preset(name, seed=1), preset(name, seed=2)
+    dx = a.lx / a.nx
+    assert a.v_table.tobytes() == b.v_table.tobytes()
+    assert a.w_top.tobytes() == b.w_top.tobytes()
+    for key in ("xa", "xb"):
+        assert a.info[key] != b.info[key]
+    base = preset(name, seed=0)
+    for w in (a, b, base):
+        assert abs(w.info["xa"] + 0.25 * w.lx) <= 0.5 * dx
+        assert abs(w.info["xb"] - 0.25 * w.lx - w.info["shift_nm"]) <= 0.5 * dx
+    assert not np.array_equal(a.psi_a, b.psi_a)
+
+
+@pytest.mark.parametrize("name", CHEAP)
+def test_preset_invariants(name):
+    w = preset(name)
+    assert w.name == name and name in PRESETS
+    assert w.v_table.shape == w.psi_a.shape == w.psi_b.shape == w.w_top.shape == (w.nx, w.ny)
+    assert w.psi_a.dtype == np.complex128 and w.v_table.dtype == np.float64
+    assert np.all(np.isfinite(w.v_table))
+    for psi in (w.psi_a, w.psi_b):
+        assert abs(np.sum(np.abs(psi) ** 2) - 1.0) < 1e-13
+    assert set(np.unique(w.w_top)) <= {0.0, 0.5, 1.0}
+    # the two packets start on opposite edges: alpha on top, beta on the bottom (the
+    # 16x16 smoke grid is too coarse to confine them, the others hold 99 % on their edge)
+    top_a = np.sum(np.abs(w.psi_a) ** 2 * w.w_top)
+    top_b = np.sum(np.abs(w.psi_b) ** 2 * w.w_top)
+    lim = 0.35 if name == "tiny" else 0.01
+    assert top_a > 1.0 - lim and top_b < lim
+
+
+def test_overrides_and_unknown_name():
+    w = preset("qpc", sigma_x=12.5, steps=7, coulomb_c=1.0)
+    assert (w.sigma_x, w.steps, w.coulomb_c) == (12.5, 7, 1.0)
+    with pytest.raises(KeyError):
+        preset("nonexistent")
+
+
+def test_mid_sweep_is_fixed():
+    s = mid_sweep()
+    assert s == mid_sweep() and len(s) == 9
+    assert all(3.0 <= v0 < 5.0 for v0, _ in s)
+    assert [sig for _, sig in s] == [10.0, 20.0, 40.0] * 3
