@@ -17,6 +17,11 @@
 // reverse order) brings every thread back to the elements it loaded.  Between
 // stages the line is exchanged through LDS, each stage reading and writing its
 // own disjoint set of positions.
+//
+// The arithmetic is FP64 for both storage types.  With complex64 storage the
+// exchange area holds complex64 too: each exchange then rounds like one more
+// store of the state (random, not coherent, since the state changes every
+// step), and the area takes half the LDS, so twice as many blocks fit a CU.
 #pragma once
 
 #include "axis_pass.hpp"
@@ -39,7 +44,8 @@ template <class S, int AXIS, int R1, int R2, int R3, int T, int VK>
 __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     using NT = Net3<R1, R2, R3, T>;
     constexpr int N = NT::N, N2 = NT::N2, JA = NT::JA, G1 = NT::G1, G2 = NT::G2, E = NT::E;
-    extern __shared__ double2 lds[];
+    using X = Xchg<S>;
+    extern __shared__ double2 lds_raw[];
 
     const int W = a.W;
     const int tid = threadIdx.x;
@@ -57,7 +63,9 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     // twiddles w_n^j (and, on y axes, the kinetic factor) staged after the exchange area
     constexpr bool KT_LDS = (AXIS == AX_Y1 || AXIS == AX_Y2);
     const int LS = W + 1;  // padded LDS row: one line position across the block's W lines
-    double2* twl = lds + N * LS;
+    typename X::T* lds = reinterpret_cast<typename X::T*>(lds_raw);
+    double2* twl = reinterpret_cast<double2*>(reinterpret_cast<char*>(lds_raw) +
+                                              axis3_xchg_bytes(N, W, sizeof(typename X::T) == 8));
     for (int i = tid; i < (KT_LDS ? 2 * N : N); i += T * W) {
         double2 w;
         if (i < N) {
@@ -69,7 +77,8 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
         twl[i] = w;
     }
     __syncthreads();
-    auto L = [&](int pos) -> double2& { return lds[pos * LS + cl]; };
+    auto Lw = [&](int pos, double2 v) { lds[pos * LS + cl] = X::put(v); };
+    auto Lr = [&](int pos) -> double2 { return X::get(lds[pos * LS + cl]); };
 
     S* ps = reinterpret_cast<S*>(a.psi) + lg.base;
     double2 v[E];
@@ -98,7 +107,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 #pragma unroll
         for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmul(v[jj * R1 + k1], twl[(jc * k1) % N]);
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) L(k1 * N2 + jc) = v[jj * R1 + k1];
+        for (int k1 = 0; k1 < R1; ++k1) Lw(k1 * N2 + jc, v[jj * R1 + k1]);
     }
     __syncthreads();
 
@@ -107,12 +116,12 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     for (int ii = 0; ii < G1; ++ii) {
         const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
 #pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) v[ii * R2 + n2] = L(k1 * N2 + n2 * R3 + j3);
+        for (int n2 = 0; n2 < R2; ++n2) v[ii * R2 + n2] = Lr(k1 * N2 + n2 * R3 + j3);
         dft<R2, -1>(&v[ii * R2]);
 #pragma unroll
         for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmul(v[ii * R2 + k2], twl[(R1 * j3 * k2) % N]);
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) L(k1 * N2 + k2 * R3 + j3) = v[ii * R2 + k2];
+        for (int k2 = 0; k2 < R2; ++k2) Lw(k1 * N2 + k2 * R3 + j3, v[ii * R2 + k2]);
     }
     __syncthreads();
 
@@ -125,7 +134,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     for (int ii = 0; ii < G2; ++ii) {
         const int q = t + T * ii, k1 = q / R2, k2 = q % R2;
 #pragma unroll
-        for (int j3 = 0; j3 < R3; ++j3) v[ii * R3 + j3] = L(k1 * N2 + k2 * R3 + j3);
+        for (int j3 = 0; j3 < R3; ++j3) v[ii * R3 + j3] = Lr(k1 * N2 + k2 * R3 + j3);
         dft<R3, -1>(&v[ii * R3]);
 #pragma unroll
         for (int k3 = 0; k3 < R3; ++k3) {
@@ -141,7 +150,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
         }
         dft<R3, 1>(&v[ii * R3]);
 #pragma unroll
-        for (int j3 = 0; j3 < R3; ++j3) L(k1 * N2 + k2 * R3 + j3) = v[ii * R3 + j3];
+        for (int j3 = 0; j3 < R3; ++j3) Lw(k1 * N2 + k2 * R3 + j3, v[ii * R3 + j3]);
     }
     __syncthreads();
 
@@ -150,12 +159,12 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     for (int ii = 0; ii < G1; ++ii) {
         const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) v[ii * R2 + k2] = L(k1 * N2 + k2 * R3 + j3);
+        for (int k2 = 0; k2 < R2; ++k2) v[ii * R2 + k2] = Lr(k1 * N2 + k2 * R3 + j3);
 #pragma unroll
         for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmulc(v[ii * R2 + k2], twl[(R1 * j3 * k2) % N]);
         dft<R2, 1>(&v[ii * R2]);
 #pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) L(k1 * N2 + n2 * R3 + j3) = v[ii * R2 + n2];
+        for (int n2 = 0; n2 < R2; ++n2) Lw(k1 * N2 + n2 * R3 + j3, v[ii * R2 + n2]);
     }
     __syncthreads();
 
@@ -164,7 +173,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     for (int jj = 0; jj < JA; ++jj) {
         const int jc = t + T * jj;
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) v[jj * R1 + k1] = L(k1 * N2 + jc);
+        for (int k1 = 0; k1 < R1; ++k1) v[jj * R1 + k1] = Lr(k1 * N2 + jc);
 #pragma unroll
         for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmulc(v[jj * R1 + k1], twl[(jc * k1) % N]);
         dft<R1, 1>(&v[jj * R1]);

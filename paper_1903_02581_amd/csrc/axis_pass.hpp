@@ -35,6 +35,22 @@ __device__ __forceinline__ void st<float2>(float2* p, double2 v) {
     *p = make_float2((float)v.x, (float)v.y);
 }
 
+// Element type of an LDS exchange of the state: complex64 with complex64
+// storage (the exchange rounds like one more store of the state), complex128
+// otherwise.  The arithmetic is FP64 either way.
+template <class S>
+struct Xchg {
+    using T = double2;
+    __device__ static __forceinline__ T put(double2 v) { return v; }
+    __device__ static __forceinline__ double2 get(T v) { return v; }
+};
+template <>
+struct Xchg<float2> {
+    using T = float2;
+    __device__ static __forceinline__ T put(double2 v) { return make_float2((float)v.x, (float)v.y); }
+    __device__ static __forceinline__ double2 get(T v) { return make_double2((double)v.x, (double)v.y); }
+};
+
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 
 // Im(conj(l) * p)

@@ -140,7 +140,7 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
         if (axis == AX_X2) w = std::min<int64_t>(w, ilog2_pow2_divisor(ny));
         p.W = (int)std::max<int64_t>(w, 1);
-        p.lds = ((size_t)p.n * (p.W + 1) + 2 * (size_t)p.n) * sizeof(double2);
+        p.lds = axis3_lds_bytes(p.n, p.W, mixed);
         return p;
     }
     int64_t w = 256 / sh.t;

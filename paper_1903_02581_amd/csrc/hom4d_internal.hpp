@@ -60,6 +60,16 @@ bool fft_shape(int n, FftShape* out);
 // kernel runs.
 int axis3_threads(int n, int nst);
 
+// LDS of the three-stage kernel: the exchange area (n positions x (W + 1)
+// slots, complex64 entries with complex64 storage, complex128 otherwise,
+// rounded up to 16 bytes), then 2n staged FP64 factors.
+__host__ __device__ constexpr size_t axis3_xchg_bytes(int n, int w, bool c64) {
+    return ((size_t)n * (size_t)(w + 1) * (c64 ? 8u : 16u) + 15u) / 16u * 16u;
+}
+__host__ __device__ constexpr size_t axis3_lds_bytes(int n, int w, bool c64) {
+    return axis3_xchg_bytes(n, w, c64) + 2u * (size_t)n * 16u;
+}
+
 // Launch one per-axis pass: blocks of t*W threads, nlines/W blocks.
 hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, int64_t nlines,
                        size_t lds_bytes, hipStream_t s);

@@ -250,6 +250,7 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
     const int64_t nblocks = nlines / a.W;
     const int max_threads = axis3_threads(n, nst) > 0 ? 512 : 256;
     if (nblocks > 0x7fffffff || t * a.W > max_threads || lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    if (axis3_threads(n, nst) > 0 && lds_bytes < axis3_lds_bytes(n, a.W, mixed)) return hipErrorInvalidValue;
     if (lds_bytes > 64 * 1024) {
         // dynamic LDS above 64 KB has to be enabled per kernel, once
         static std::mutex mu;

@@ -8,8 +8,9 @@
 //     Y2(dt):   transform along y2, kinetic phase of k_y2, inverse,
 // i.e. three consecutive factors of the Strang step (arXiv 1903.02581,
 // Sec. II.C Eq. (evoloperat); the x and y kinetic terms of Appendix A).  The
-// plane stays in LDS (FP64) between the stages; each line transform is the
-// same register/LDS four-step network as the per-axis pass.
+// plane stays in LDS between the stages, in the storage precision (Xchg); the
+// arithmetic is FP64.  Each line transform is the same register/LDS four-step
+// network as the per-axis pass.
 #pragma once
 
 #include "axis_pass.hpp"
@@ -60,7 +61,8 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     constexpr int JAY = B2 / TY, IBY = B1 / TY;
     constexpr int SLX = NY * TX, QX = (SLX + NT - 1) / NT;
     constexpr int SLY = NX * TY, QY = (SLY + NT - 1) / NT;
-    __shared__ double2 L[NX * LY::row];
+    using X = Xchg<S>;
+    __shared__ typename X::T L[NX * LY::row];
     __shared__ double2 TW[NX + 2 * NY];  // x twiddles, y twiddles, y kinetic factor
 
     const int tid = threadIdx.x;
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int jj = 0; jj < JAX; ++jj)
 #pragma unroll
-                        for (int k1 = 0; k1 < A1; ++k1) L[LY::at(k1 * A2 + t + TX * jj, c)] = vx[q][jj * A1 + k1];
+                        for (int k1 = 0; k1 < A1; ++k1) L[LY::at(k1 * A2 + t + TX * jj, c)] = X::put(vx[q][jj * A1 + k1]);
                 }
             }
             __syncthreads();
@@ -146,7 +148,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int ii = 0; ii < IBX; ++ii)
 #pragma unroll
-                        for (int j = 0; j < A2; ++j) vb[q][ii * A2 + j] = L[LY::at((t + TX * ii) * A2 + j, c)];
+                        for (int j = 0; j < A2; ++j) vb[q][ii * A2 + j] = X::get(L[LY::at((t + TX * ii) * A2 + j, c)]);
 #pragma unroll
                     for (int ii = 0; ii < IBX; ++ii) dft<A2, -1>(&vb[q][ii * A2]);
                 }
@@ -185,7 +187,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int ii = 0; ii < IBX; ++ii)
 #pragma unroll
-                        for (int j = 0; j < A2; ++j) L[LY::at((t + TX * ii) * A2 + j, c)] = vb[q][ii * A2 + j];
+                        for (int j = 0; j < A2; ++j) L[LY::at((t + TX * ii) * A2 + j, c)] = X::put(vb[q][ii * A2 + j]);
                 }
             }
             __syncthreads();
@@ -196,7 +198,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int jj = 0; jj < JAX; ++jj)
 #pragma unroll
-                        for (int k1 = 0; k1 < A1; ++k1) vb[q][jj * A1 + k1] = L[LY::at(k1 * A2 + t + TX * jj, c)];
+                        for (int k1 = 0; k1 < A1; ++k1) vb[q][jj * A1 + k1] = X::get(L[LY::at(k1 * A2 + t + TX * jj, c)]);
                 }
             }
         }
@@ -231,7 +233,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                 for (int jj = 0; jj < JAX; ++jj)
 #pragma unroll
-                    for (int n1 = 0; n1 < A1; ++n1) L[LY::at(n1 * A2 + t + TX * jj, c)] = vb[q][jj * A1 + n1];
+                    for (int n1 = 0; n1 < A1; ++n1) L[LY::at(n1 * A2 + t + TX * jj, c)] = X::put(vb[q][jj * A1 + n1]);
             }
         }
         __syncthreads();
@@ -246,7 +248,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                 for (int jj = 0; jj < JAY; ++jj)
 #pragma unroll
-                    for (int n1 = 0; n1 < B1; ++n1) vy[q][jj * B1 + n1] = L[LY::at(row, n1 * B2 + t + TY * jj)];
+                    for (int n1 = 0; n1 < B1; ++n1) vy[q][jj * B1 + n1] = X::get(L[LY::at(row, n1 * B2 + t + TY * jj)]);
 #pragma unroll
                 for (int jj = 0; jj < JAY; ++jj) {
                     dft<B1, -1>(&vy[q][jj * B1]);
@@ -268,7 +270,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int jj = 0; jj < JAY; ++jj)
 #pragma unroll
-                        for (int k1 = 0; k1 < B1; ++k1) L[LY::at(row, k1 * B2 + t + TY * jj)] = vy[q][jj * B1 + k1];
+                        for (int k1 = 0; k1 < B1; ++k1) L[LY::at(row, k1 * B2 + t + TY * jj)] = X::put(vy[q][jj * B1 + k1]);
                 }
             }
             __syncthreads();
@@ -280,7 +282,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int ii = 0; ii < IBY; ++ii)
 #pragma unroll
-                        for (int j = 0; j < B2; ++j) vy[q][ii * B2 + j] = L[LY::at(row, (t + TY * ii) * B2 + j)];
+                        for (int j = 0; j < B2; ++j) vy[q][ii * B2 + j] = X::get(L[LY::at(row, (t + TY * ii) * B2 + j)]);
 #pragma unroll
                     for (int ii = 0; ii < IBY; ++ii) dft<B2, -1>(&vy[q][ii * B2]);
                 }
@@ -312,7 +314,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int ii = 0; ii < IBY; ++ii)
 #pragma unroll
-                        for (int j = 0; j < B2; ++j) L[LY::at(row, (t + TY * ii) * B2 + j)] = vy[q][ii * B2 + j];
+                        for (int j = 0; j < B2; ++j) L[LY::at(row, (t + TY * ii) * B2 + j)] = X::put(vy[q][ii * B2 + j]);
                 }
             }
             __syncthreads();
@@ -324,7 +326,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int jj = 0; jj < JAY; ++jj)
 #pragma unroll
-                        for (int k1 = 0; k1 < B1; ++k1) vy[q][jj * B1 + k1] = L[LY::at(row, k1 * B2 + t + TY * jj)];
+                        for (int k1 = 0; k1 < B1; ++k1) vy[q][jj * B1 + k1] = X::get(L[LY::at(row, k1 * B2 + t + TY * jj)]);
                 }
             }
         }
