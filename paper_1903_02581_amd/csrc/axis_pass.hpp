@@ -180,7 +180,11 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     constexpr int JA = N2 / T;  // stage-A columns per thread
     constexpr int IB = N1 / T;  // stage-B rows per thread
     static_assert(N1 % T == 0 && N2 % T == 0, "t must divide both factors");
-    extern __shared__ double2 lds[];
+    // complex64 exchanges with complex64 storage, except on the x1 pass, which
+    // measured slower with them (48x48: 27.7 -> 32.8 us)
+    using X = Xchg<typename std::conditional<axis_xchg_c64(AXIS, true), S, double2>::type>;
+    extern __shared__ double2 lds_raw[];
+    typename X::T* lds = reinterpret_cast<typename X::T*>(lds_raw);
 
     const int W = a.W;
     const int tid = threadIdx.x;
@@ -203,7 +207,8 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     // electron 1 along the line, exp(-i tau V(x1, y1) / hbar) for every y1, is one
     // table row: staged after the kinetic factor instead of read per element.
     constexpr bool A1_LDS = (AXIS == AX_Y1 && VK == 1);
-    double2* TWL = lds + (N2 > 1 ? NST * N * (W + 1) : 0);
+    double2* TWL = reinterpret_cast<double2*>(reinterpret_cast<char*>(lds_raw) +
+                                              axis_xchg_bytes(N2 > 1 ? N : 0, W, NST, sizeof(typename X::T) == 8));
     const int a1_row = A1_LDS ? (int)((blockIdx.x * (uint32_t)W) / ((uint32_t)a.nx * (uint32_t)a.ny)) * a.ny : 0;
     for (int i = tid; i < (KT_LDS ? 2 * N : N) + (A1_LDS ? N : 0); i += T * W) {
         double2 v;
@@ -291,14 +296,14 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
             for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
                 for (int k1 = 0; k1 < N1; ++k1)
-                    lds[(s * N + k1 * N2 + t + T * jj) * LS + cl] = v[s][jj * N1 + k1];
+                    lds[(s * N + k1 * N2 + t + T * jj) * LS + cl] = X::put(v[s][jj * N1 + k1]);
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < NST; ++s)
 #pragma unroll
             for (int ii = 0; ii < IB; ++ii)
 #pragma unroll
-                for (int j = 0; j < N2; ++j) v[s][ii * N2 + j] = lds[(s * N + (t + T * ii) * N2 + j) * LS + cl];
+                for (int j = 0; j < N2; ++j) v[s][ii * N2 + j] = X::get(lds[(s * N + (t + T * ii) * N2 + j) * LS + cl]);
         // stage B: DFT_n2 over the columns; element (ii, k2) is wave number k1 + n1 * k2
 #pragma unroll
         for (int s = 0; s < NST; ++s)
@@ -356,7 +361,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
 #pragma unroll
             for (int ii = 0; ii < IB; ++ii)
 #pragma unroll
-                for (int j = 0; j < N2; ++j) lds[(s * N + (t + T * ii) * N2 + j) * LS + cl] = v[s][ii * N2 + j];
+                for (int j = 0; j < N2; ++j) lds[(s * N + (t + T * ii) * N2 + j) * LS + cl] = X::put(v[s][ii * N2 + j]);
         __syncthreads();
 #pragma unroll
         for (int s = 0; s < NST; ++s)
@@ -364,7 +369,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
             for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
                 for (int k1 = 0; k1 < N1; ++k1)
-                    v[s][jj * N1 + k1] = lds[(s * N + k1 * N2 + t + T * jj) * LS + cl];
+                    v[s][jj * N1 + k1] = X::get(lds[(s * N + k1 * N2 + t + T * jj) * LS + cl]);
     }
 #pragma unroll
     for (int s = 0; s < NST; ++s) {
@@ -410,7 +415,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     }
 
     if constexpr (NST == 2) {
-        double* red = reinterpret_cast<double*>(lds);
+        double* red = reinterpret_cast<double*>(lds_raw);
         if (a.gflags & G_GB) {
             const double s = block_sum(gb_acc, red);
             if (tid == 0) a.gb_part[blockIdx.x] += s;

@@ -145,8 +145,10 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
     }
     int64_t w = 256 / sh.t;
     if (sh.n2 > 1) {
-        // LDS per block: 64 KB for complex128 storage (W = 16 lines already gives
-        // 256-byte runs), 80 KB for complex64 (two blocks per CU, W = 32 on n = 128)
+        // widths from an LDS budget counted in complex128 exchange entries: 64 KB
+        // for complex128 storage (W = 16 lines already gives 256-byte runs), 80 KB
+        // for complex64 (W = 32 on n = 128), whose blocks then take half of it
+        // since they exchange complex64
         const int64_t budget = mixed ? 81920 : 65536;
         const int64_t cap = (budget - 3 * p.n * 16) / ((int64_t)nst * p.n * 16) - 1;
         while (w > cap) w >>= 1;
@@ -160,7 +162,7 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
     // exchange area, then the staged twiddles, kinetic factor and (y1) one-body
     // factor row (3n entries); the dual-state reduction scratch reuses the start
     // of the allocation at the end
-    const size_t ex = sh.n2 > 1 ? (size_t)nst * p.n * (p.W + 1) * sizeof(double2) : 0;
+    const size_t ex = axis_xchg_bytes(sh.n2 > 1 ? p.n : 0, p.W, nst, axis_xchg_c64(axis, mixed));
     const size_t red = nst == 2 ? (size_t)sh.t * p.W * sizeof(double) : 0;
     p.lds = std::max(ex + (size_t)3 * p.n * sizeof(double2), red);
     return p;

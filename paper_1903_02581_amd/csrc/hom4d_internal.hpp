@@ -60,6 +60,16 @@ bool fft_shape(int n, FftShape* out);
 // kernel runs.
 int axis3_threads(int n, int nst);
 
+// Whether the two-stage kernel's exchanges on this axis are complex64 (with
+// complex64 storage: every axis but x1).
+__host__ __device__ constexpr bool axis_xchg_c64(int axis, bool mixed) { return mixed && axis != AX_X1; }
+
+// Exchange area of the two-stage kernel: nst states x n positions x (W + 1)
+// slots (n = 0 where the line needs no exchange), entries as above.
+__host__ __device__ constexpr size_t axis_xchg_bytes(int n, int w, int nst, bool c64) {
+    return ((size_t)nst * (size_t)n * (size_t)(w + 1) * (c64 ? 8u : 16u) + 15u) / 16u * 16u;
+}
+
 // LDS of the three-stage kernel: the exchange area (n positions x (W + 1)
 // slots, complex64 entries with complex64 storage, complex128 otherwise,
 // rounded up to 16 bytes), then 2n staged FP64 factors.

@@ -250,7 +250,14 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
     const int64_t nblocks = nlines / a.W;
     const int max_threads = axis3_threads(n, nst) > 0 ? 512 : 256;
     if (nblocks > 0x7fffffff || t * a.W > max_threads || lds_bytes > 160 * 1024) return hipErrorInvalidValue;
-    if (axis3_threads(n, nst) > 0 && lds_bytes < axis3_lds_bytes(n, a.W, mixed)) return hipErrorInvalidValue;
+    if (axis3_threads(n, nst) > 0) {
+        if (lds_bytes < axis3_lds_bytes(n, a.W, mixed)) return hipErrorInvalidValue;
+    } else {
+        FftShape sh;
+        if (!fft_shape(n, &sh)) return hipErrorInvalidValue;
+        const size_t need = axis_xchg_bytes(sh.n2 > 1 ? n : 0, a.W, nst, axis_xchg_c64(axis, mixed)) + 3u * (size_t)n * 16u;
+        if (lds_bytes < need) return hipErrorInvalidValue;
+    }
     if (lds_bytes > 64 * 1024) {
         // dynamic LDS above 64 KB has to be enabled per kernel, once
         static std::mutex mu;
