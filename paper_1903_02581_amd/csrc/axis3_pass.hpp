@@ -88,14 +88,23 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
         for (int n1 = 0; n1 < R1; ++n1) v[jj * R1 + n1] = ld<S>(ps + (int64_t)(n1 * N2 + t + T * jj) * lg.sN);
 
     auto potential = [&]() {
+        if constexpr (VK == 1) {
+            const LineTables<AXIS> tb(a, lg, t);
 #pragma unroll
-        for (int jj = 0; jj < JA; ++jj)
+            for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
-            for (int n1 = 0; n1 < R1; ++n1) {
-                int c[4];
-                elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, n1 * N2 + t + T * jj, c);
-                v[jj * R1 + n1] = cmul(v[jj * R1 + n1], vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]));
-            }
+                for (int n1 = 0; n1 < R1; ++n1)
+                    v[jj * R1 + n1] = cmul(v[jj * R1 + n1], tb.at(n1 * N2 + T * jj, a.kconj));
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+                for (int n1 = 0; n1 < R1; ++n1) {
+                    int c[4];
+                    elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, n1 * N2 + t + T * jj, c);
+                    v[jj * R1 + n1] = cmul(v[jj * R1 + n1], vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]));
+                }
+        }
     };
     if (VK != 0 && a.vmode == 1) potential();
 
@@ -105,7 +114,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
         const int jc = t + T * jj;
         dft<R1, -1>(&v[jj * R1]);
 #pragma unroll
-        for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmul(v[jj * R1 + k1], twl[(jc * k1) % N]);
+        for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmul(v[jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) Lw(k1 * N2 + jc, v[jj * R1 + k1]);
     }
@@ -119,7 +128,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
         for (int n2 = 0; n2 < R2; ++n2) v[ii * R2 + n2] = Lr(k1 * N2 + n2 * R3 + j3);
         dft<R2, -1>(&v[ii * R2]);
 #pragma unroll
-        for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmul(v[ii * R2 + k2], twl[(R1 * j3 * k2) % N]);
+        for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmul(v[ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) Lw(k1 * N2 + k2 * R3 + j3, v[ii * R2 + k2]);
     }
@@ -161,7 +170,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) v[ii * R2 + k2] = Lr(k1 * N2 + k2 * R3 + j3);
 #pragma unroll
-        for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmulc(v[ii * R2 + k2], twl[(R1 * j3 * k2) % N]);
+        for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmulc(v[ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
         dft<R2, 1>(&v[ii * R2]);
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) Lw(k1 * N2 + n2 * R3 + j3, v[ii * R2 + n2]);
@@ -175,7 +184,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) v[jj * R1 + k1] = Lr(k1 * N2 + jc);
 #pragma unroll
-        for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmulc(v[jj * R1 + k1], twl[(jc * k1) % N]);
+        for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmulc(v[jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
         dft<R1, 1>(&v[jj * R1]);
     }
 

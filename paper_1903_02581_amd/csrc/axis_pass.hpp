@@ -440,6 +440,41 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     }
 }
 
+// Table form of the potential factor along one line (VK = 1 of vfactor, same
+// products in the same order): element m of a line along AXIS reads a1 at r1(m),
+// a1 at r2(m) and ac at r1(m) - r2(m), each index affine in m.  The line's
+// fixed coordinates and the thread's first element m0 give three base pointers
+// once; element m0 + dm then adds dm times a per-axis step, a uniform product
+// when dm is a compile-time offset.
+template <int AXIS>
+struct LineTables {
+    const double2* p1;
+    const double2* p2;
+    const double2* pc;
+    int64_t step;  // index step of the varying electron's a1 entry (ny on x axes, 1 on y axes)
+    int64_t cstep; // index step of ac (+-(2 ny - 1) on x axes, +-1 on y axes)
+    __device__ __forceinline__ LineTables(const PassArgs& a, const LineGeom<AXIS>& lg, int m0) {
+        int c[4];
+        elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, m0, c);
+        const int64_t ny = a.ny, cy = 2 * (int64_t)a.ny - 1;
+        p1 = a.a1 + (c[0] * ny + c[1]);
+        p2 = a.a1 + (c[2] * ny + c[3]);
+        pc = a.ac ? a.ac + ((int64_t)(c[0] - c[2] + a.nx - 1) * cy + (c[1] - c[3] + a.ny - 1)) : nullptr;
+        step = (AXIS == AX_X1 || AXIS == AX_X2) ? ny : 1;
+        cstep = (AXIS == AX_X1) ? cy : (AXIS == AX_X2) ? -cy : (AXIS == AX_Y1) ? 1 : -1;
+    }
+    __device__ __forceinline__ double2 at(int dm, bool conj) const {
+        const int64_t o = dm * step;
+        double2 f;
+        if constexpr (AXIS == AX_X1 || AXIS == AX_Y1)
+            f = cmul(p1[o], p2[0]);
+        else
+            f = cmul(p1[0], p2[o]);
+        if (pc) f = cmul(f, pc[dm * cstep]);
+        return conj ? conjd(f) : f;
+    }
+};
+
 using AxisKernel = void (*)(const PassArgs);
 
 template <class S, int AXIS, int NST, int VK>
