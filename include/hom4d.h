@@ -57,6 +57,8 @@ extern "C" {
 #define HOM4D_EHIP (-5)        /* HIP runtime error; detail in hom4d_last_error() */
 #define HOM4D_ENONFINITE (-6)  /* the state holds a NaN or Inf */
 #define HOM4D_ENORMDRIFT (-7)  /* |norm - 1| above the watchdog tolerance */
+#define HOM4D_ECONFIG (-8)     /* checkpoint image taken with another configuration */
+#define HOM4D_ECORRUPT (-9)    /* checkpoint image fails its checksum or norm check */
 
 #define HOM4D_FP64 0           /* complex128 state */
 #define HOM4D_MIXED 1          /* complex64 state, FP64 arithmetic */
@@ -132,6 +134,27 @@ int hom4d_init_state(hom4d* h, const double* psi_a, const double* psi_b, int32_t
  * load resets the step count; in MIXED the values are rounded to complex64. */
 int hom4d_load_state(hom4d* h, const double* psi4d);
 int hom4d_store_state(hom4d* h, double* psi4d);
+
+/* Checkpoint images for resuming a long run (not an operation of the paper:
+ * its propagations take thousands of steps, Sec. III).  An image is a 64-byte
+ * header -- magic "HOM4DCK1", version 1, precision, nx, ny, step count, a
+ * 64-bit hash of the configuration fields, the current B and the potential
+ * table, the payload size, a Fletcher-style checksum of the payload and the
+ * FP64 norm of the state -- followed by the state in its storage precision
+ * ([x1][y1][x2][y2], complex128 or complex64, bit for bit).  The buffer is
+ * caller-owned host memory of hom4d_checkpoint_bytes(h) bytes (0 for a NULL
+ * handle).  save: ENOMEM if the buffer is smaller, ENONFINITE if the state is
+ * not finite; synchronises.  load: EINVAL if the buffer is not an image or is
+ * truncated, ECONFIG if it was taken with another size, precision,
+ * configuration, field or potential (the bound state is then untouched),
+ * ECORRUPT if the payload fails its checksum (untouched) or the norm
+ * recomputed on the GPU after the copy differs from the recorded one by more
+ * than 1e-12 relative (the state is then the damaged copy); on success the
+ * state and the step count are the saved ones and any gradient recording is
+ * discarded.  Synchronises. */
+size_t hom4d_checkpoint_bytes(const hom4d* h);
+int hom4d_save_checkpoint(hom4d* h, void* buf, size_t bytes);
+int hom4d_load_checkpoint(hom4d* h, const void* buf, size_t bytes);
 
 /* Advance the bound state by n >= 0 whole steps S(dt); asynchronous on the
  * stream.  While a gradient recording is open, also stores the checkpoints. */

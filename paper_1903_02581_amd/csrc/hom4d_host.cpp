@@ -209,6 +209,7 @@ struct hom4d {
     void* psi = nullptr;
     int64_t step = 0;
     bool have_v = false;
+    uint64_t v_hash = 0;         // FNV-1a of the last potential table (0: none)
     double norm_tol = 1e-6;
     int pass_plan = 0;           // 0: fused plane pass where built, 1: per-axis passes only
     bool plane_built = false;    // a fused plane kernel exists for (nx, ny, precision)
@@ -530,6 +531,68 @@ int gather(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1, const int32_t*
     return HOM4D_OK;
 }
 
+// 64-bit FNV-1a, continued from h.
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+// Everything a resumed run must share with the saved one: the configuration
+// fields one by one (no struct padding), the current field B and the potential.
+uint64_t config_hash(const hom4d* h) {
+    const hom4d_cfg& c = h->cfg;
+    uint64_t x = fnv1a(&c.nx, sizeof c.nx);
+    x = fnv1a(&c.ny, sizeof c.ny, x);
+    x = fnv1a(&c.precision, sizeof c.precision, x);
+    x = fnv1a(&c.coulomb_mode, sizeof c.coulomb_mode, x);
+    const double d[] = {c.lx_nm, c.ly_nm, c.mstar_rel, c.eps_r, c.b_tesla, c.dt_fs, c.soft_nm, c.coulomb_c, c.screen_nm};
+    x = fnv1a(d, sizeof d, x);
+    return fnv1a(&h->v_hash, sizeof h->v_hash, x);
+}
+
+// Fletcher-style sum over 64-bit words (every single-bit change and every
+// reordering of words changes it); n is a multiple of 8.
+uint64_t payload_sum(const void* p, size_t n, uint64_t s1 = 0, uint64_t s2 = 0) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; i += 8) {
+        uint64_t w;
+        std::memcpy(&w, b + i, 8);
+        s1 += w;
+        s2 += s1;
+    }
+    return s1 ^ ((s2 << 32) | (s2 >> 32));
+}
+
+// Checkpoint image header (64 bytes), followed by the state in its storage precision.
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t precision;
+    int32_t nx, ny;
+    int64_t step;
+    uint64_t config_hash;
+    uint64_t payload_bytes;
+    uint64_t payload_sum;
+    double norm;
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
+constexpr char kCkptMagic[8] = {'H', 'O', 'M', '4', 'D', 'C', 'K', '1'};
+
+// FP64 norm of the bound state (one reduction pass).
+int state_norm(hom4d* h, double* out) {
+    HIP_TRY(hipMemsetAsync(h->w_dev, 0, h->nxy * sizeof(double), h->stream));
+    HIP_TRY(launch_obs(h->psi, h->mixed, h->w_dev, h->nxy, h->red_part, h->red_blocks, h->stream));
+    double r[5];
+    int rc = fetch_reduction(h, 5, r);
+    if (rc) return rc;
+    *out = r[0];
+    return HOM4D_OK;
+}
+
 void free_all(hom4d* h) {
     void* bufs[] = {h->tw_x, h->tw_y, h->kx_half, h->kx_full, h->kxt_half, h->kxt_full, h->ky_full, h->a1_half, h->ac_half, h->v_dev,
                     h->w_dev, h->red_part, h->red_out, h->ix_dev, h->slice_dev, h->orb_dev, h->g_buf};
@@ -648,6 +711,7 @@ int hom4d_set_potential(hom4d* h, const double* v) {
     rc = upload(h, h->v_dev, v, (size_t)c.nx * c.ny * sizeof(double));
     if (rc) return rc;
     h->have_v = true;
+    h->v_hash = fnv1a(v, (size_t)c.nx * c.ny * sizeof(double));
     return HOM4D_OK;
 }
 
@@ -727,6 +791,72 @@ int hom4d_store_state(hom4d* h, double* psi4d) {
             for (int64_t i = 0; i < 2 * m; ++i) psi4d[2 * o + i] = (double)buf[i];
         }
     }
+    return HOM4D_OK;
+}
+
+size_t hom4d_checkpoint_bytes(const hom4d* h) { return h ? sizeof(CkptHeader) + h->state_bytes : 0; }
+
+int hom4d_save_checkpoint(hom4d* h, void* buf, size_t bytes) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!buf) return fail(HOM4D_EINVAL, "buffer is NULL");
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    if (bytes < sizeof(CkptHeader) + h->state_bytes)
+        return fail(HOM4D_ENOMEM, "checkpoint buffer of %zu bytes, %zu needed", bytes,
+                    sizeof(CkptHeader) + h->state_bytes);
+    double nrm = 0.0;
+    int rc = state_norm(h, &nrm);
+    if (rc) return rc;
+    if (!std::isfinite(nrm)) return fail(HOM4D_ENONFINITE, "state holds non-finite values");
+    char* payload = static_cast<char*>(buf) + sizeof(CkptHeader);
+    HIP_TRY(hipMemcpyAsync(payload, h->psi, h->state_bytes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    CkptHeader hd{};
+    std::memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = 1;
+    hd.precision = h->cfg.precision;
+    hd.nx = h->cfg.nx;
+    hd.ny = h->cfg.ny;
+    hd.step = h->step;
+    hd.config_hash = config_hash(h);
+    hd.payload_bytes = h->state_bytes;
+    hd.payload_sum = payload_sum(payload, h->state_bytes);
+    hd.norm = nrm;
+    std::memcpy(buf, &hd, sizeof hd);
+    return HOM4D_OK;
+}
+
+int hom4d_load_checkpoint(hom4d* h, const void* buf, size_t bytes) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!buf) return fail(HOM4D_EINVAL, "buffer is NULL");
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    CkptHeader hd;
+    if (bytes < sizeof hd) return fail(HOM4D_EINVAL, "%zu bytes: shorter than a checkpoint header", bytes);
+    std::memcpy(&hd, buf, sizeof hd);
+    if (std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1)
+        return fail(HOM4D_EINVAL, "not a checkpoint image of this library");
+    if (hd.precision != h->cfg.precision || hd.nx != h->cfg.nx || hd.ny != h->cfg.ny ||
+        hd.payload_bytes != h->state_bytes)
+        return fail(HOM4D_ECONFIG, "checkpoint of a %dx%d %s state, handle is %dx%d %s", hd.nx, hd.ny,
+                    hd.precision == HOM4D_MIXED ? "complex64" : "complex128", h->cfg.nx, h->cfg.ny,
+                    h->mixed ? "complex64" : "complex128");
+    if (hd.config_hash != config_hash(h))
+        return fail(HOM4D_ECONFIG, "checkpoint taken with other parameters, field or potential");
+    if (bytes < sizeof hd + hd.payload_bytes)
+        return fail(HOM4D_EINVAL, "%zu bytes: the image is truncated (%zu expected)", bytes,
+                    (size_t)(sizeof hd + hd.payload_bytes));
+    const char* payload = static_cast<const char*>(buf) + sizeof hd;
+    if (payload_sum(payload, h->state_bytes) != hd.payload_sum)
+        return fail(HOM4D_ECORRUPT, "checkpoint payload does not match its checksum");
+    HIP_TRY(hipMemcpyAsync(h->psi, payload, h->state_bytes, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->rec = false;
+    double nrm = 0.0;
+    int rc = state_norm(h, &nrm);
+    if (rc) return rc;
+    if (!std::isfinite(nrm)) return fail(HOM4D_ENONFINITE, "restored state holds non-finite values");
+    if (!(std::fabs(nrm - hd.norm) <= 1e-12 * std::fabs(hd.norm)))
+        return fail(HOM4D_ECORRUPT, "restored state has norm %.17g, the image recorded %.17g", nrm, hd.norm);
+    h->step = hd.step;
     return HOM4D_OK;
 }
 
@@ -1003,6 +1133,8 @@ const char* hom4d_strerror(int status) {
         case HOM4D_EHIP: return "HIP runtime error";
         case HOM4D_ENONFINITE: return "non-finite state";
         case HOM4D_ENORMDRIFT: return "norm drift beyond tolerance";
+        case HOM4D_ECONFIG: return "checkpoint from another configuration";
+        case HOM4D_ECORRUPT: return "checkpoint corrupted";
         default: return "unknown status";
     }
 }

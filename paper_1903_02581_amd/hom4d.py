@@ -23,11 +23,13 @@ COULOMB_TABLE = 0
 COULOMB_DIRECT = 1
 
 STATUS = {0: "HOM4D_OK", -1: "HOM4D_EINVAL", -2: "HOM4D_EUNBOUND", -3: "HOM4D_ESTATE",
-          -4: "HOM4D_ENOMEM", -5: "HOM4D_EHIP", -6: "HOM4D_ENONFINITE", -7: "HOM4D_ENORMDRIFT"}
+          -4: "HOM4D_ENOMEM", -5: "HOM4D_EHIP", -6: "HOM4D_ENONFINITE", -7: "HOM4D_ENORMDRIFT",
+          -8: "HOM4D_ECONFIG", -9: "HOM4D_ECORRUPT"}
 
 EXPORTS = ["hom4d_create", "hom4d_destroy", "hom4d_validate_cfg", "hom4d_state_bytes",
            "hom4d_bind_state", "hom4d_set_potential", "hom4d_set_field", "hom4d_init_state",
-           "hom4d_load_state", "hom4d_store_state", "hom4d_step", "hom4d_observables",
+           "hom4d_load_state", "hom4d_store_state", "hom4d_checkpoint_bytes",
+           "hom4d_save_checkpoint", "hom4d_load_checkpoint", "hom4d_step", "hom4d_observables",
            "hom4d_set_norm_tol", "hom4d_entanglement", "hom4d_gather_slice", "hom4d_marginal",
            "hom4d_conditional", "hom4d_grad_begin",
            "hom4d_grad_backward", "hom4d_grad_end", "hom4d_run_pass", "hom4d_set_pass_plan",
@@ -79,6 +81,9 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "hom4d_init_state": ([vp, dp, dp, c_int32], c_int),
         "hom4d_load_state": ([vp, dp], c_int),
         "hom4d_store_state": ([vp, dp], c_int),
+        "hom4d_checkpoint_bytes": ([vp], c_size_t),
+        "hom4d_save_checkpoint": ([vp, vp, c_size_t], c_int),
+        "hom4d_load_checkpoint": ([vp, vp, c_size_t], c_int),
         "hom4d_step": ([vp, c_int64], c_int),
         "hom4d_observables": ([vp, dp, POINTER(HomObs)], c_int),
         "hom4d_set_norm_tol": ([vp, c_double], c_int),
@@ -207,6 +212,20 @@ class Propagator:
         out = np.empty(n * n, dtype=np.complex128)
         self._check(self.lib.hom4d_store_state(self.h, _dptr(out.view(np.float64))), "store_state")
         return out.reshape(self.nx, self.ny, self.nx, self.ny)
+
+    def save_checkpoint(self) -> np.ndarray:
+        """Checkpoint image of the state (header + state bits) as a uint8 array."""
+        nb = int(self.lib.hom4d_checkpoint_bytes(self.h))
+        buf = np.empty(nb, dtype=np.uint8)
+        self._check(self.lib.hom4d_save_checkpoint(self.h, c_void_p(buf.ctypes.data), nb),
+                    "save_checkpoint")
+        return buf
+
+    def load_checkpoint(self, image):
+        """Restore a checkpoint image (state and step count); the library checks it."""
+        buf = np.ascontiguousarray(np.asarray(image, dtype=np.uint8)).ravel()
+        self._check(self.lib.hom4d_load_checkpoint(self.h, c_void_p(buf.ctypes.data), buf.size),
+                    "load_checkpoint")
 
     def step(self, n: int = 1):
         self._check(self.lib.hom4d_step(self.h, int(n)), "step")

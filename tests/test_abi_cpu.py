@@ -32,7 +32,7 @@ def test_header_symbols_exported():
 
 def test_status_strings():
     lib = _lib()
-    for code in range(0, -8, -1):
+    for code in range(0, -10, -1):
         s = lib.hom4d_strerror(code)
         assert s and s != b"unknown status"
     assert lib.hom4d_strerror(-99) == b"unknown status"
@@ -84,3 +84,11 @@ def test_soft_zero_allowed_without_coulomb():
     lib = _lib()
     cfg = make_cfg(16, 16, 100.0, 100.0, dt_fs=1.0, b_tesla=5.0, soft_nm=0.0, coulomb_c=0.0)
     assert lib.hom4d_validate_cfg(ctypes.byref(cfg)) == 0
+
+
+def test_checkpoint_calls_reject_null_handle():
+    lib = _lib()
+    assert lib.hom4d_checkpoint_bytes(None) == 0
+    buf = ctypes.create_string_buffer(128)
+    assert lib.hom4d_save_checkpoint(None, buf, 128) == -1
+    assert lib.hom4d_load_checkpoint(None, buf, 128) == -1
