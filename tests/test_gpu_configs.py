@@ -182,6 +182,45 @@ def test_full_scale_short_run():
         torch.cuda.empty_cache()
 
 
+def test_maximum_size_256x256():
+    """The largest supported grid, 256x256 per electron: 4.3e9 points, past 32-bit point
+    indices (a complex128 state of 68.7 GB, complex64 34.4 GB).  Both precisions against the
+    2D oracle through the V12 = 0 factorisation, on sampled points and P_TT."""
+    from workloads.presets import build
+    from paper_1903_02581_amd import Propagator
+    import torch
+    w = build("max", 256, 256, 2000.0, 2000.0, b_tesla=5.0, dt_fs=0.5, steps=3, sigma_x=20.0,
+              coulomb_c=0.0, seed=5)
+    announce(f"maximum size 256x256 ({w.points} points) V12=0 steps={w.steps} both precisions")
+    a, b, scale = _factorised_reference(w, w.steps)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-4)):
+        p = Propagator.from_workload(w, precision=prec)
+        assert p.passes_per_step == 4
+        p.step(w.steps)
+        o = p.observables(w.w_top)
+        flat = p.psi
+        assert flat.numel() == w.points
+
+        def get(idx):
+            return flat[torch.as_tensor(idx, device=flat.device)].cpu().numpy().astype(np.complex128)
+
+        # samples reach the last r1 rows, beyond 2^32 elements
+        p_tt = _check_factorised(get, w, a, b, scale, tol)
+        r1 = np.arange(w.nx * w.ny - 64, w.nx * w.ny)
+        r2 = np.arange(64)
+        af, bf = a.ravel(), b.ravel()
+        ref = (af[r1] * bf[r2] - bf[r1] * af[r2]) / scale
+        got = get(r1 * (w.nx * w.ny) + r2)
+        amp = np.max(np.abs(af)) * np.max(np.abs(bf)) / scale      # scale of |Psi| anywhere
+        assert np.max(np.abs(got - ref)) <= tol * amp
+        assert abs(o["p_tt"] - p_tt) <= tol
+        assert abs(o["norm"] - 1.0) <= (1e-10 if prec == "fp64" else 1e-4)
+        announce(f"maximum size {prec}: norm-1={o['norm'] - 1:.2e} P_TT={o['p_tt']:.10f} (2D oracle {p_tt:.10f})")
+        p.close()
+        del p, flat
+        torch.cuda.empty_cache()
+
+
 def test_diff_config_gradient_vs_finite_differences():
     """48x48 per electron, 1000 steps, checkpoint every 100: adjoint dP_b/d(V0, V1, sx, sy, B)
     against central differences (h = 1e-4 relative) of the FP64 GPU forward run, and the

@@ -196,6 +196,22 @@ def test_resume_from_stored_state_is_bitwise(name, precision):
         assert o_resumed[key] == o_straight[key], key
 
 
+def test_step_zero_is_identity():
+    # step(0) applies nothing: not even the opening and closing half-step x factors
+    from paper_1903_02581_amd import Propagator
+    w = preset("tiny")
+    announce("step(0) identity (tiny, both plans)")
+    for plan in (0, 1):
+        p = Propagator.from_workload(w)
+        p.set_pass_plan(plan)
+        p.step(2)
+        before = p.store_state()
+        p.step(0)
+        assert np.array_equal(p.store_state(), before)
+        assert p.observables(w.w_top)["step"] == 2
+        p.close()
+
+
 def test_watchdog_and_errors():
     from paper_1903_02581_amd import Propagator, Hom4dError
     w = preset("tiny")
