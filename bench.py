@@ -16,7 +16,8 @@ region.  value = grid-point-steps per second = (nx ny)^2 * steps / time.
 Extra objects on the JSON line:
   roofline     -- the dominant pass kernel, timed with HIP events on the
                   library's stream, against the 8 TB/s HBM peak (and, for
-                  context, against a measured 1 GiB device copy);
+                  context, against a measured 1 GiB device copy), plus the
+                  whole step's algorithmic bytes per second (step_GBps);
   cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same workload;
   mixed        -- the complex64-storage form on the same workload and its error
                   against the FP64 GPU run (|dP_b|, relative L2 of psi, norm).
@@ -352,7 +353,13 @@ def main():
                      "traffic": (traffic["bytes_per_launch"][dom] if traffic else None),
                      "kernel": f"pass kernel {dom}", "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_s": passes[dom], "pass_seconds": passes,
-                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     # the whole step: every pass's algorithmic bytes over the timed step
+                     # time (observable sampling included); a state near the 256 MB
+                     # Infinity Cache (64x64 FP64: 268 MB) partly hits it, so this can
+                     # exceed what HBM alone delivers
+                     "step_GBps": alg_bytes * passes_per_step / (sec / args.steps) / 1e9,
+                     "step_frac": alg_bytes * passes_per_step / (sec / args.steps) / 1e9 / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
         "mixed": mixed,
         "extras": extras,
