@@ -47,8 +47,10 @@ struct PlaneLds {
 };
 
 // One plane per workgroup, grid = nx * ny.  Barriers: one after every LDS write
-// that other threads read back; none before a write, because each exchange
-// writes exactly the positions the same thread read in the previous one.
+// that other wavefronts read back (the row exchanges of the Y2 stage stay
+// inside one wavefront and only wait for its own writes); none before a write,
+// because each exchange writes exactly the positions the same thread read in
+// the previous one.
 template <class S, int NX, int NY, int NT, int VK>
 __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     using SX_ = Shape<NX>;
@@ -239,6 +241,19 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
         __syncthreads();
 
         // ---------------- Y2 stage: lines along y2, one per x2 (row of the plane)
+        // When every row's TY threads sit in one wavefront and each wavefront owns
+        // whole rows, the row exchanges stay inside the wavefront: it waits for its
+        // own LDS writes before it reads (the memory clobber keeps the compiler
+        // from moving or forwarding LDS accesses across the wait); no workgroup
+        // barrier.  (The column exchanges of the X2 stage span wavefronts: a
+        // column-per-wavefront thread mapping measured slower, 127 -> 150 us.)
+        constexpr bool Y_WAVE = (QY == 1) && (64 % TY == 0);
+        auto y_sync = [&]() {
+            if constexpr (Y_WAVE)
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            else
+                __syncthreads();
+        };
         double2 vy[QY][EY];
 #pragma unroll
         for (int q = 0; q < QY; ++q) {
@@ -273,7 +288,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                         for (int k1 = 0; k1 < B1; ++k1) L[LY::at(row, k1 * B2 + t + TY * jj)] = X::put(vy[q][jj * B1 + k1]);
                 }
             }
-            __syncthreads();
+            y_sync();
 #pragma unroll
             for (int q = 0; q < QY; ++q) {
                 const int s = tid + NT * q;
@@ -317,7 +332,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                         for (int j = 0; j < B2; ++j) L[LY::at(row, (t + TY * ii) * B2 + j)] = X::put(vy[q][ii * B2 + j]);
                 }
             }
-            __syncthreads();
+            y_sync();
 #pragma unroll
             for (int q = 0; q < QY; ++q) {
                 const int s = tid + NT * q;
