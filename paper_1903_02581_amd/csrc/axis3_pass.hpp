@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) Lw(k1 * N2 + jc, v[jj * R1 + k1]);
     }
-    __syncthreads();
+    line_sync<AXIS, T>();
 
     // ---- stage B1 (forward), in place on its positions
 #pragma unroll
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) Lw(k1 * N2 + k2 * R3 + j3, v[ii * R2 + k2]);
     }
-    __syncthreads();
+    line_sync<AXIS, T>();
 
     // ---- stage B2: forward, kinetic phase at k = k1 + R1 (k2 + R2 k3), inverse
     // x kinetic factor table: y-major [y][k] on the x1 pass, k-major [k][y] on the x2 pass
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 #pragma unroll
         for (int j3 = 0; j3 < R3; ++j3) Lw(k1 * N2 + k2 * R3 + j3, v[ii * R3 + j3]);
     }
-    __syncthreads();
+    line_sync<AXIS, T>();
 
     // ---- stage B1 (inverse)
 #pragma unroll
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) Lw(k1 * N2 + n2 * R3 + j3, v[ii * R2 + n2]);
     }
-    __syncthreads();
+    line_sync<AXIS, T>();
 
     // ---- stage A (inverse), back on the loaded elements
 #pragma unroll

@@ -97,6 +97,19 @@ __device__ __forceinline__ double2 vfactor(const PassArgs& a, int i1, int j1, in
     return f;
 }
 
+// Synchronisation after an LDS exchange of a line pass.  Lines along y2 put a
+// line's T threads on consecutive lanes, so with T dividing 64 every wavefront
+// owns whole lines: it only waits for its own LDS writes before reading (the
+// memory clobber keeps the compiler from moving or forwarding LDS accesses
+// across the wait).  On the other axes a line spans wavefronts.
+template <int AXIS, int T>
+__device__ __forceinline__ void line_sync() {
+    if constexpr (AXIS == AX_Y2 && 64 % T == 0)
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    else
+        __syncthreads();
+}
+
 // Sum over the block, valid in thread 0.  blockDim.x is a power of two.
 __device__ inline double block_sum(double v, double* red) {
     const int tid = threadIdx.x;
@@ -297,7 +310,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
 #pragma unroll
                 for (int k1 = 0; k1 < N1; ++k1)
                     lds[(s * N + k1 * N2 + t + T * jj) * LS + cl] = X::put(v[s][jj * N1 + k1]);
-        __syncthreads();
+        line_sync<AXIS, T>();
 #pragma unroll
         for (int s = 0; s < NST; ++s)
 #pragma unroll
@@ -362,7 +375,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
             for (int ii = 0; ii < IB; ++ii)
 #pragma unroll
                 for (int j = 0; j < N2; ++j) lds[(s * N + (t + T * ii) * N2 + j) * LS + cl] = X::put(v[s][ii * N2 + j]);
-        __syncthreads();
+        line_sync<AXIS, T>();
 #pragma unroll
         for (int s = 0; s < NST; ++s)
 #pragma unroll
