@@ -184,25 +184,28 @@ def config_throughput(name, precision, steps, plan=None, **overrides):
     return out
 
 
-def adjoint_throughput(precision):
-    """Forward with checkpoints + reverse sweep on the 48x48, 1000-step gradient workload."""
+def adjoint_throughput(precision, name="diff", steps=None, ckpt=None):
+    """Forward with checkpoints + reverse sweep: the 48x48, 1000-step gradient workload, or
+    a short recording on another workload (the 256x128 one: 20 steps, checkpoint every 10)."""
     import torch
     from workloads import preset
-    w = preset("diff")
+    w = preset(name)
+    steps = steps or w.steps
+    ckpt = ckpt or w.ckpt_every
     p = make_prop(w, precision)
     p.set_norm_tol(1.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    p.grad_begin(w.ckpt_every, w.steps)
-    p.step(w.steps)
+    p.grad_begin(ckpt, steps)
+    p.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     loss, dldv, dldb = p.grad_backward(w.w_top)
     t2 = time.perf_counter()
     p.close()
-    return {"workload": "diff: 48x48, 1000 steps, checkpoint every 100", "precision": precision,
-            "forward_s": t1 - t0, "backward_s": t2 - t1,
-            "backward_gp_steps_per_s": w.points * w.steps / (t2 - t1),
+    return {"workload": f"{name}: {w.nx}x{w.ny}, {steps} steps, checkpoint every {ckpt}",
+            "precision": precision, "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "backward_gp_steps_per_s": w.points * steps / (t2 - t1),
             "loss_p_b": loss, "dL_dB": dldb, "sum_dL_dV": float(dldv.sum()),
             "sum_abs_dL_dV": float(np.abs(dldv).sum())}
 
@@ -319,7 +322,8 @@ def main():
                 config_throughput("qpc", "fp64", 300, coulomb_c=1.0),
                 config_throughput("qpc", "mixed", 300, coulomb_c=1.0),
             ],
-            "adjoint": [adjoint_throughput("fp64"), adjoint_throughput("mixed")],
+            "adjoint": [adjoint_throughput("fp64"), adjoint_throughput("mixed"),
+                        adjoint_throughput("mixed", "full", 20, 10)],
         }
 
     cpu = None

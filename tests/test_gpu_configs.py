@@ -263,3 +263,45 @@ def test_diff_config_gradient_vs_finite_differences():
     scale = np.max(np.abs(g64))
     assert np.max(np.abs(g64 - fd)) <= 1e-5 * scale
     assert np.max(np.abs(g32 - g64)) <= 1e-3 * scale
+
+
+def test_full_scale_adjoint():
+    """256x128 per electron (1.07e9 points), the adjoint over 20 recorded steps (checkpoint
+    every 10): FP64 against complex64, the gauge identity sum dL/dV = 0, and dL/dB against a
+    central difference of two FP64 forward runs (B +- 1e-4 relative)."""
+    import torch
+    from paper_1903_02581_amd import Propagator
+    w = preset("full")
+    steps, ck = 20, 10
+    announce(f"full 256x128 adjoint steps={steps} ckpt={ck} both precisions + FD in B")
+    res = {}
+    for prec in ("fp64", "mixed"):
+        p = Propagator.from_workload(w, precision=prec)
+        p.set_norm_tol(1.0)
+        p.grad_begin(ck, steps)
+        p.step(steps)
+        res[prec] = p.grad_backward(w.w_top)
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+    (l64, v64, b64), (l32, v32, b32) = res["fp64"], res["mixed"]
+    assert np.all(np.isfinite(v64)) and np.isfinite(b64)
+    assert abs(v64.sum()) <= 1e-10 * np.abs(v64).sum()
+    assert abs(l32 - l64) <= 1e-6 * max(abs(l64), 1e-12) + 1e-12
+    assert np.max(np.abs(v32 - v64)) <= 1e-4 * np.max(np.abs(v64))
+    assert abs(b32 - b64) <= 1e-4 * abs(b64)
+    h = 1e-4 * w.b_tesla
+    lf = []
+    for sgn in (1.0, -1.0):
+        p = Propagator.from_workload(w)
+        p.set_norm_tol(1.0)
+        p.set_field(w.b_tesla + sgn * h)
+        p.step(steps)
+        o = p.observables(w.w_top)
+        lf.append(o["p_b"])
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+    fd = (lf[0] - lf[1]) / (2 * h)
+    announce(f"full adjoint: L={l64:.6e} dL/dB adjoint {b64:.6e} (mixed {b32:.6e}) FD {fd:.6e}")
+    assert abs(fd - b64) <= 1e-4 * abs(b64)
