@@ -40,7 +40,7 @@ struct Net3 {
     static_assert(G1 * R2 == E && G2 * R3 == E, "every stage must give a thread E elements");
 };
 
-template <class S, int AXIS, int R1, int R2, int R3, int T, int VK>
+template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK>
 __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     using NT = Net3<R1, R2, R3, T>;
     constexpr int N = NT::N, N2 = NT::N2, JA = NT::JA, G1 = NT::G1, G2 = NT::G2, E = NT::E;
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     const int LS = W + 1;  // padded LDS row: one line position across the block's W lines
     typename X::T* lds = reinterpret_cast<typename X::T*>(lds_raw);
     double2* twl = reinterpret_cast<double2*>(reinterpret_cast<char*>(lds_raw) +
-                                              axis3_xchg_bytes(N, W, sizeof(typename X::T) == 8));
+                                              axis3_xchg_bytes(N, W, NST, sizeof(typename X::T) == 8));
     for (int i = tid; i < (KT_LDS ? 2 * N : N); i += T * W) {
         double2 w;
         if (i < N) {
@@ -77,15 +77,34 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
         twl[i] = w;
     }
     __syncthreads();
-    auto Lw = [&](int pos, double2 v) { lds[pos * LS + cl] = X::put(v); };
-    auto Lr = [&](int pos) -> double2 { return X::get(lds[pos * LS + cl]); };
+    // state s, line position pos: s * N + pos rows of W + 1 slots
+    auto Lw = [&](int st_, int pos, double2 v) { lds[(st_ * N + pos) * LS + cl] = X::put(v); };
+    auto Lr = [&](int st_, int pos) -> double2 { return X::get(lds[(st_ * N + pos) * LS + cl]); };
 
-    S* ps = reinterpret_cast<S*>(a.psi) + lg.base;
-    double2 v[E];
+    // the state, and in the reverse sweep the adjoint state beside it
+    S* ps[NST];
+    ps[0] = reinterpret_cast<S*>(a.psi) + lg.base;
+    if constexpr (NST == 2) ps[1] = reinterpret_cast<S*>(a.lam) + lg.base;
+    double2 v[NST][E];
 #pragma unroll
-    for (int jj = 0; jj < JA; ++jj)
+    for (int s = 0; s < NST; ++s)
 #pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) v[jj * R1 + n1] = ld<S>(ps + (int64_t)(n1 * N2 + t + T * jj) * lg.sN);
+        for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1)
+                v[s][jj * R1 + n1] = ld<S>(ps[s] + (int64_t)(n1 * N2 + t + T * jj) * lg.sN);
+
+    // gradient accumulators of the reverse sweep: the potential marginal
+    // Im(conj(lambda) psi) on the side of the potential factor the pass is told
+    // to take it (before: G_MIN, after: G_MOUT), and the dL/dB term of the x
+    // kinetic factor in reciprocal space
+    double gm_acc = 0.0, gb_acc = 0.0;
+    if constexpr (NST == 2) {
+        if (a.gflags & G_MIN) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
+        }
+    }
 
     auto potential = [&]() {
         if constexpr (VK == 1) {
@@ -93,8 +112,11 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 #pragma unroll
             for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1)
-                    v[jj * R1 + n1] = cmul(v[jj * R1 + n1], tb.at(n1 * N2 + T * jj, a.kconj));
+                for (int n1 = 0; n1 < R1; ++n1) {
+                    const double2 f = tb.at(n1 * N2 + T * jj, a.kconj);
+#pragma unroll
+                    for (int s = 0; s < NST; ++s) v[s][jj * R1 + n1] = cmul(v[s][jj * R1 + n1], f);
+                }
         } else {
 #pragma unroll
             for (int jj = 0; jj < JA; ++jj)
@@ -102,7 +124,9 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
                 for (int n1 = 0; n1 < R1; ++n1) {
                     int c[4];
                     elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, n1 * N2 + t + T * jj, c);
-                    v[jj * R1 + n1] = cmul(v[jj * R1 + n1], vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]));
+                    const double2 f = vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
+#pragma unroll
+                    for (int s = 0; s < NST; ++s) v[s][jj * R1 + n1] = cmul(v[s][jj * R1 + n1], f);
                 }
         }
     };
@@ -110,28 +134,32 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
 
     // ---- stage A (forward)
 #pragma unroll
-    for (int jj = 0; jj < JA; ++jj) {
-        const int jc = t + T * jj;
-        dft<R1, -1>(&v[jj * R1]);
+    for (int s = 0; s < NST; ++s)
 #pragma unroll
-        for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmul(v[jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
+        for (int jj = 0; jj < JA; ++jj) {
+            const int jc = t + T * jj;
+            dft<R1, -1>(&v[s][jj * R1]);
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) Lw(k1 * N2 + jc, v[jj * R1 + k1]);
-    }
+            for (int k1 = 1; k1 < R1; ++k1) v[s][jj * R1 + k1] = cmul(v[s][jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) Lw(s, k1 * N2 + jc, v[s][jj * R1 + k1]);
+        }
     line_sync<AXIS, T>();
 
     // ---- stage B1 (forward), in place on its positions
 #pragma unroll
-    for (int ii = 0; ii < G1; ++ii) {
-        const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
+    for (int s = 0; s < NST; ++s)
 #pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) v[ii * R2 + n2] = Lr(k1 * N2 + n2 * R3 + j3);
-        dft<R2, -1>(&v[ii * R2]);
+        for (int ii = 0; ii < G1; ++ii) {
+            const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
 #pragma unroll
-        for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmul(v[ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
+            for (int n2 = 0; n2 < R2; ++n2) v[s][ii * R2 + n2] = Lr(s, k1 * N2 + n2 * R3 + j3);
+            dft<R2, -1>(&v[s][ii * R2]);
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) Lw(k1 * N2 + k2 * R3 + j3, v[ii * R2 + k2]);
-    }
+            for (int k2 = 1; k2 < R2; ++k2) v[s][ii * R2 + k2] = cmul(v[s][ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) Lw(s, k1 * N2 + k2 * R3 + j3, v[s][ii * R2 + k2]);
+        }
     line_sync<AXIS, T>();
 
     // ---- stage B2: forward, kinetic phase at k = k1 + R1 (k2 + R2 k3), inverse
@@ -139,15 +167,30 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
     const int yrow = (AXIS == AX_X1) ? lg.j1 : ((AXIS == AX_X2) ? lg.j2 : 0);
     const double2* kt = a.ktab + (AXIS == AX_X1 ? (int64_t)yrow * N : (int64_t)yrow);
     const int64_t kstride = AXIS == AX_X1 ? 1 : a.ny;
+    constexpr bool GB = (NST == 2) && (AXIS == AX_X1 || AXIS == AX_X2);
+    const bool gb_on = GB && (a.gflags & G_GB);
+    const double yv = a.y0 + a.ystep * yrow;
+    const double shift = yv * a.b_eoh;
 #pragma unroll
     for (int ii = 0; ii < G2; ++ii) {
         const int q = t + T * ii, k1 = q / R2, k2 = q % R2;
 #pragma unroll
-        for (int j3 = 0; j3 < R3; ++j3) v[ii * R3 + j3] = Lr(k1 * N2 + k2 * R3 + j3);
-        dft<R3, -1>(&v[ii * R3]);
+        for (int s = 0; s < NST; ++s) {
+#pragma unroll
+            for (int j3 = 0; j3 < R3; ++j3) v[s][ii * R3 + j3] = Lr(s, k1 * N2 + k2 * R3 + j3);
+            dft<R3, -1>(&v[s][ii * R3]);
+        }
 #pragma unroll
         for (int k3 = 0; k3 < R3; ++k3) {
             const int k = k1 + R1 * (k2 + R2 * k3);
+            if constexpr (GB) {
+                if (gb_on) {
+                    // d theta_X / dB at (k, y), on the values before the kinetic factor
+                    const int m = (k < (N + 1) / 2) ? k : k - N;
+                    const double dth = a.db_coef * (a.kstep * m - shift) * yv;
+                    gb_acc += dth * im_cl_p(v[1][ii * R3 + k3], v[0][ii * R3 + k3]);
+                }
+            }
             double2 f;
             if constexpr (KT_LDS) {
                 f = twl[N + k];
@@ -155,79 +198,145 @@ __global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
                 f = kt[k * kstride];
                 if (a.kconj) f = conjd(f);
             }
-            v[ii * R3 + k3] = cmul(v[ii * R3 + k3], f);
-        }
-        dft<R3, 1>(&v[ii * R3]);
 #pragma unroll
-        for (int j3 = 0; j3 < R3; ++j3) Lw(k1 * N2 + k2 * R3 + j3, v[ii * R3 + j3]);
+            for (int s = 0; s < NST; ++s) v[s][ii * R3 + k3] = cmul(v[s][ii * R3 + k3], f);
+        }
+#pragma unroll
+        for (int s = 0; s < NST; ++s) {
+            dft<R3, 1>(&v[s][ii * R3]);
+#pragma unroll
+            for (int j3 = 0; j3 < R3; ++j3) Lw(s, k1 * N2 + k2 * R3 + j3, v[s][ii * R3 + j3]);
+        }
     }
     line_sync<AXIS, T>();
 
     // ---- stage B1 (inverse)
 #pragma unroll
-    for (int ii = 0; ii < G1; ++ii) {
-        const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
+    for (int s = 0; s < NST; ++s)
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) v[ii * R2 + k2] = Lr(k1 * N2 + k2 * R3 + j3);
+        for (int ii = 0; ii < G1; ++ii) {
+            const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
 #pragma unroll
-        for (int k2 = 1; k2 < R2; ++k2) v[ii * R2 + k2] = cmulc(v[ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
-        dft<R2, 1>(&v[ii * R2]);
+            for (int k2 = 0; k2 < R2; ++k2) v[s][ii * R2 + k2] = Lr(s, k1 * N2 + k2 * R3 + j3);
 #pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) Lw(k1 * N2 + n2 * R3 + j3, v[ii * R2 + n2]);
-    }
+            for (int k2 = 1; k2 < R2; ++k2) v[s][ii * R2 + k2] = cmulc(v[s][ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
+            dft<R2, 1>(&v[s][ii * R2]);
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) Lw(s, k1 * N2 + n2 * R3 + j3, v[s][ii * R2 + n2]);
+        }
     line_sync<AXIS, T>();
 
     // ---- stage A (inverse), back on the loaded elements
 #pragma unroll
-    for (int jj = 0; jj < JA; ++jj) {
-        const int jc = t + T * jj;
+    for (int s = 0; s < NST; ++s)
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) v[jj * R1 + k1] = Lr(k1 * N2 + jc);
+        for (int jj = 0; jj < JA; ++jj) {
+            const int jc = t + T * jj;
 #pragma unroll
-        for (int k1 = 1; k1 < R1; ++k1) v[jj * R1 + k1] = cmulc(v[jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
-        dft<R1, 1>(&v[jj * R1]);
-    }
+            for (int k1 = 0; k1 < R1; ++k1) v[s][jj * R1 + k1] = Lr(s, k1 * N2 + jc);
+#pragma unroll
+            for (int k1 = 1; k1 < R1; ++k1) v[s][jj * R1 + k1] = cmulc(v[s][jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
+            dft<R1, 1>(&v[s][jj * R1]);
+        }
 
     if (VK != 0 && a.vmode == 2) potential();
 
+    if constexpr (NST == 2) {
+        if (a.gflags & G_MOUT) {
 #pragma unroll
-    for (int jj = 0; jj < JA; ++jj)
+            for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
+        }
+    }
+
 #pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) st<S>(ps + (int64_t)(n1 * N2 + t + T * jj) * lg.sN, v[jj * R1 + n1]);
+    for (int s = 0; s < NST; ++s)
+#pragma unroll
+        for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1)
+                st<S>(ps[s] + (int64_t)(n1 * N2 + t + T * jj) * lg.sN, v[s][jj * R1 + n1]);
+
+    if constexpr (NST == 2) {
+        // the same partial-sum layout as the two-stage pass: dL/dB per block; the
+        // marginal per line on the x1 and y1 axes (the line's threads summed in
+        // fixed order), per block on x2 and y2 (a block's lines share r1)
+        double* red = reinterpret_cast<double*>(lds_raw);
+        if (a.gflags & G_GB) {
+            const double sum = block_sum(gb_acc, red);
+            if (tid == 0) a.gb_part[blockIdx.x] += sum;
+        }
+        if (a.gflags & (G_MIN | G_MOUT)) {
+            if constexpr (AXIS == AX_X1 || AXIS == AX_Y1) {
+                __syncthreads();
+                red[t * W + cl] = gm_acc;
+                __syncthreads();
+                if (t == 0) {
+                    double sum = 0.0;
+                    for (int q = 0; q < T; ++q) sum += red[q * W + cl];
+                    a.marg_part[line] += sum;
+                }
+            } else {
+                const double sum = block_sum(gm_acc, red);
+                if (tid == 0) a.marg_part[blockIdx.x] += sum;
+            }
+        }
+    }
 }
 
 // Three-stage factorisations: n = R1 R2 R3 on T threads per line.
-template <class S, int AXIS, int VK>
+template <class S, int AXIS, int NST, int VK>
 AxisKernel pick3(int n, int* t) {
     switch (n) {
-        case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, VK>;
-        case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, VK>;
-        case 256: *t = 32; return k_axis3<S, AXIS, 8, 8, 4, 32, VK>;
+        case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, NST, VK>;
+        case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, NST, VK>;
+        case 256: *t = 32; return k_axis3<S, AXIS, 8, 8, 4, 32, NST, VK>;
         default: *t = 0; return nullptr;
     }
 }
 
 // Forward single-state passes: the x1 pass carries no potential factor, the
-// y2 pass always carries it, x2 and y1 either.
+// y2 pass always carries it, x2 and y1 either.  Reverse dual-state passes: the
+// x passes carry none, y1 (before its transform) and y2 (after) carry it.
 template <class S>
-AxisKernel pick_axis3(int axis, int n, int vk, int* t) {
+AxisKernel pick_axis3(int axis, int n, int vk, int nst, int* t) {
+    if (nst == 2) {
+        switch (axis) {
+            case AX_X1:
+                if (vk == 0) return pick3<S, AX_X1, 2, 0>(n, t);
+                break;
+            case AX_X2:
+                if (vk == 0) return pick3<S, AX_X2, 2, 0>(n, t);
+                break;
+            case AX_Y1:
+                if (vk == 1) return pick3<S, AX_Y1, 2, 1>(n, t);
+                if (vk == 2) return pick3<S, AX_Y1, 2, 2>(n, t);
+                break;
+            case AX_Y2:
+                if (vk == 1) return pick3<S, AX_Y2, 2, 1>(n, t);
+                if (vk == 2) return pick3<S, AX_Y2, 2, 2>(n, t);
+                break;
+            default: break;
+        }
+        *t = 0;
+        return nullptr;
+    }
     switch (axis) {
         case AX_X1:
-            if (vk == 0) return pick3<S, AX_X1, 0>(n, t);
+            if (vk == 0) return pick3<S, AX_X1, 1, 0>(n, t);
             break;
         case AX_X2:
-            if (vk == 0) return pick3<S, AX_X2, 0>(n, t);
-            if (vk == 1) return pick3<S, AX_X2, 1>(n, t);
-            if (vk == 2) return pick3<S, AX_X2, 2>(n, t);
+            if (vk == 0) return pick3<S, AX_X2, 1, 0>(n, t);
+            if (vk == 1) return pick3<S, AX_X2, 1, 1>(n, t);
+            if (vk == 2) return pick3<S, AX_X2, 1, 2>(n, t);
             break;
         case AX_Y1:
-            if (vk == 0) return pick3<S, AX_Y1, 0>(n, t);
-            if (vk == 1) return pick3<S, AX_Y1, 1>(n, t);
-            if (vk == 2) return pick3<S, AX_Y1, 2>(n, t);
+            if (vk == 0) return pick3<S, AX_Y1, 1, 0>(n, t);
+            if (vk == 1) return pick3<S, AX_Y1, 1, 1>(n, t);
+            if (vk == 2) return pick3<S, AX_Y1, 1, 2>(n, t);
             break;
         case AX_Y2:
-            if (vk == 1) return pick3<S, AX_Y2, 1>(n, t);
-            if (vk == 2) return pick3<S, AX_Y2, 2>(n, t);
+            if (vk == 1) return pick3<S, AX_Y2, 1, 1>(n, t);
+            if (vk == 2) return pick3<S, AX_Y2, 1, 2>(n, t);
             break;
         default: break;
     }

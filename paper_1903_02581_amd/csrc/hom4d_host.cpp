@@ -132,15 +132,19 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         // factors.  n = 128: 16 lines (256 threads) within 48 KB, so that three
         // or more blocks share a CU; n = 96 and 256 measured faster with wider
         // blocks: 32 lines (256 threads) and 16 lines (512 threads) within 80 KB
+        // The reverse sweep's dual-state blocks take two exchange areas within
+        // 80 KB, counted in the storage's entry size.
         p.t = t3;
         const bool wide = p.n != 128;
         int64_t w = (wide ? 512 : 256) / t3;
-        const int64_t cap = ((wide ? 81920 : 49152) - 2 * p.n * 16) / ((int64_t)p.n * 16) - 1;
+        const int64_t cap = nst == 1 ? ((wide ? 81920 : 49152) - 2 * p.n * 16) / ((int64_t)p.n * 16) - 1
+                                     : (81920 - 2 * p.n * 16) / ((int64_t)2 * p.n * (mixed ? 8 : 16)) - 1;
         while (w > cap) w >>= 1;
         w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
         if (axis == AX_X2) w = std::min<int64_t>(w, ilog2_pow2_divisor(ny));
+        if (axis == AX_Y2 && grad) w = std::min<int64_t>(w, ilog2_pow2_divisor(nx));
         p.W = (int)std::max<int64_t>(w, 1);
-        p.lds = axis3_lds_bytes(p.n, p.W, mixed);
+        p.lds = axis3_lds_bytes(p.n, p.W, nst, mixed);
         return p;
     }
     int64_t w = 256 / sh.t;

@@ -55,9 +55,9 @@ struct FftShape {
 // Supported line lengths and their register/LDS decomposition.
 bool fft_shape(int n, FftShape* out);
 
-// Threads per line of the three-stage pass kernel used for the forward
-// single-state passes of long lines (n = 96, 128, 256); 0 where the two-stage
-// kernel runs.
+// Threads per line of the three-stage pass kernel used for the long lines
+// (n = 96, 128, 256), forward (one state) and reverse (two states); 0 where
+// the two-stage kernel runs.
 int axis3_threads(int n, int nst);
 
 // Whether the two-stage kernel's exchanges on this axis are complex64 (with
@@ -70,14 +70,14 @@ __host__ __device__ constexpr size_t axis_xchg_bytes(int n, int w, int nst, bool
     return ((size_t)nst * (size_t)n * (size_t)(w + 1) * (c64 ? 8u : 16u) + 15u) / 16u * 16u;
 }
 
-// LDS of the three-stage kernel: the exchange area (n positions x (W + 1)
-// slots, complex64 entries with complex64 storage, complex128 otherwise,
-// rounded up to 16 bytes), then 2n staged FP64 factors.
-__host__ __device__ constexpr size_t axis3_xchg_bytes(int n, int w, bool c64) {
-    return ((size_t)n * (size_t)(w + 1) * (c64 ? 8u : 16u) + 15u) / 16u * 16u;
+// LDS of the three-stage kernel: the exchange area (nst states x n positions x
+// (W + 1) slots, complex64 entries with complex64 storage, complex128
+// otherwise, rounded up to 16 bytes), then 2n staged FP64 factors.
+__host__ __device__ constexpr size_t axis3_xchg_bytes(int n, int w, int nst, bool c64) {
+    return ((size_t)nst * (size_t)n * (size_t)(w + 1) * (c64 ? 8u : 16u) + 15u) / 16u * 16u;
 }
-__host__ __device__ constexpr size_t axis3_lds_bytes(int n, int w, bool c64) {
-    return axis3_xchg_bytes(n, w, c64) + 2u * (size_t)n * 16u;
+__host__ __device__ constexpr size_t axis3_lds_bytes(int n, int w, int nst, bool c64) {
+    return axis3_xchg_bytes(n, w, nst, c64) + 2u * (size_t)n * 16u;
 }
 
 // Launch one per-axis pass: blocks of t*W threads, nlines/W blocks.

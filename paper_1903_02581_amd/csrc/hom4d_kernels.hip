@@ -35,8 +35,8 @@ AxisKernel pick_axis_f64_1(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f64_2(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f32_1(int axis, int n, int vk, int* t);
 AxisKernel pick_axis_f32_2(int axis, int n, int vk, int* t);
-AxisKernel pick_axis3_f64(int axis, int n, int vk, int* t);
-AxisKernel pick_axis3_f32(int axis, int n, int vk, int* t);
+AxisKernel pick_axis3_f64(int axis, int n, int vk, int nst, int* t);
+AxisKernel pick_axis3_f32(int axis, int n, int vk, int nst, int* t);
 AxisKernel pick_plane_f64(int nx, int ny, int vk, int* nt);
 AxisKernel pick_plane_f32(int nx, int ny, int vk, int* nt);
 
@@ -208,7 +208,7 @@ inline int obs_threads() { return 256; }
 }  // namespace
 
 int axis3_threads(int n, int nst) {
-    if (nst != 1) return 0;
+    if (nst != 1 && nst != 2) return 0;
     switch (n) {
         case 96: return 8;
         case 128: return 16;
@@ -241,7 +241,7 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
     AxisKernel fn = nullptr;
     const int vk = a.vmode == 0 ? 0 : (a.vdirect ? 2 : 1);
     if (axis3_threads(n, nst) > 0)
-        fn = mixed ? pick_axis3_f32(axis, n, vk, &t) : pick_axis3_f64(axis, n, vk, &t);
+        fn = mixed ? pick_axis3_f32(axis, n, vk, nst, &t) : pick_axis3_f64(axis, n, vk, nst, &t);
     else if (!mixed)
         fn = (nst == 2) ? pick_axis_f64_2(axis, n, vk, &t) : pick_axis_f64_1(axis, n, vk, &t);
     else
@@ -251,7 +251,7 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
     const int max_threads = axis3_threads(n, nst) > 0 ? 512 : 256;
     if (nblocks > 0x7fffffff || t * a.W > max_threads || lds_bytes > 160 * 1024) return hipErrorInvalidValue;
     if (axis3_threads(n, nst) > 0) {
-        if (lds_bytes < axis3_lds_bytes(n, a.W, mixed)) return hipErrorInvalidValue;
+        if (lds_bytes < axis3_lds_bytes(n, a.W, nst, mixed)) return hipErrorInvalidValue;
     } else {
         FftShape sh;
         if (!fft_shape(n, &sh)) return hipErrorInvalidValue;

@@ -16,9 +16,15 @@ def _case(nx=8, ny=8, steps=6, sym=-1, seed=1):
     return w
 
 
-@pytest.mark.parametrize("nx,ny,steps,ck,sym", [(8, 8, 6, 2, -1), (16, 8, 7, 3, -1),
-                                                (8, 12, 5, 10, 0), (12, 16, 9, 4, 1)])
-def test_grad_vs_oracle_stored_adjoint(nx, ny, steps, ck, sym):
+# The last four reach the three-stage line kernels of the reverse sweep (n = 96, 128, 256).
+# On the 128x4 and 256x4 boxes the packets barely meet the potential in a few steps: the
+# largest dL/dV is ~1e-8 of L, and FP64 cancellation in the sums leaves ~5e-10 of it
+# (the two-stage reverse kernel gives the same), hence their looser bound.
+@pytest.mark.parametrize("nx,ny,steps,ck,sym,vtol", [(8, 8, 6, 2, -1, 1e-10), (16, 8, 7, 3, -1, 1e-10),
+                                                     (8, 12, 5, 10, 0, 1e-10), (12, 16, 9, 4, 1, 1e-10),
+                                                     (128, 4, 5, 2, -1, 2e-9), (4, 96, 5, 3, -1, 1e-10),
+                                                     (256, 4, 4, 2, 1, 2e-9), (8, 128, 3, 2, 0, 1e-10)])
+def test_grad_vs_oracle_stored_adjoint(nx, ny, steps, ck, sym, vtol):
     from paper_1903_02581_amd import Propagator
     w = _case(nx, ny, steps, sym)
     announce(f"grad fp64 {nx}x{ny} steps={steps} ckpt={ck} sym={sym}")
@@ -31,7 +37,7 @@ def test_grad_vs_oracle_stored_adjoint(nx, ny, steps, ck, sym):
     p.step(steps)
     L2, gv2, gb2 = p.grad_backward(w.w_top)
     assert abs(L - L2) <= 1e-12
-    assert np.max(np.abs(gv - gv2)) <= 1e-10 * np.max(np.abs(gv))
+    assert np.max(np.abs(gv - gv2)) <= vtol * np.max(np.abs(gv))
     assert abs(gb - gb2) <= 1e-10 * max(abs(gb), 1e-12)
     assert abs(gv2.sum()) <= 1e-10 * np.abs(gv2).sum()
     # the state is back at the start of the recording
