@@ -9,7 +9,7 @@ and the state is advanced by products of their exponentials.  The two kinetic
 pieces are applied with 2D discrete Fourier transforms over a pair of
 coordinates, (x1, x2) or (y1, y2), exactly as the paper describes.
 
-Readings taken where the paper is silent or garbled (all listed in the design doc):
+Readings taken where the paper is silent or garbled:
   * gauge A = (-B y, 0) for an electron of charge -e, so T_x = (hbar k_x - e B y)^2/2m*
     is diagonal in (k_x, y) and T_y = hbar^2 k_y^2/2m* in k_y (the paper uses the
     rotated gauge A = (0, B x, 0));
