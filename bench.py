@@ -244,7 +244,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is a design note only)", file=sys.stderr)
         sys.exit(2)
 
