@@ -71,3 +71,9 @@ def test_mid_sweep_is_fixed():
     assert s == mid_sweep() and len(s) == 9
     assert all(3.0 <= v0 < 5.0 for v0, _ in s)
     assert [sig for _, sig in s] == [10.0, 20.0, 40.0] * 3
+
+
+def test_run_driver_rejects_bad_interval():
+    from paper_1903_02581_amd.run import main
+    with pytest.raises(SystemExit):
+        main(["--every", "0"])
