@@ -212,6 +212,46 @@ def test_step_zero_is_identity():
         p.close()
 
 
+# Determinism as the race detector: no float atomics, fixed-order reductions, so any
+# missing synchronisation between LDS writes and reads shows up as run-to-run differences.
+# Every supported line length on both axes, the fused plane sizes, both storages, and the
+# dual-state reverse kernels, each run twice in fresh propagators.
+REPEAT_SIZES = SIZES + [(16, 16), (24, 24), (32, 32), (48, 48), (64, 64), (48, 16), (16, 48)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bitwise_repeatable_every_size(precision):
+    from paper_1903_02581_amd import Propagator
+    announce(f"bitwise repeatability, {len(REPEAT_SIZES)} shapes, {precision}")
+    for nx, ny in REPEAT_SIZES:
+        w = build("rep", nx, ny, 10.0 * nx, 12.0 * ny, b_tesla=5.0, dt_fs=2.0, steps=3,
+                  sigma_x=max(10.0, 2.0 * nx), seed=nx * ny)
+        runs = []
+        for _ in range(2):
+            p = Propagator.from_workload(w, precision=precision)
+            p.step(3)
+            runs.append(p.store_state())
+            p.close()
+        assert np.array_equal(runs[0], runs[1]), (nx, ny, precision)
+
+
+@pytest.mark.parametrize("nx,ny", [(128, 4), (4, 96), (256, 4), (8, 128), (16, 16)])
+def test_reverse_sweep_bitwise_repeatable(nx, ny):
+    from paper_1903_02581_amd import Propagator
+    w = build("rep", nx, ny, 25.0 * nx, 25.0 * ny, b_tesla=5.0, dt_fs=5.0, steps=4,
+              sigma_x=20.0, seed=2)
+    announce(f"reverse sweep repeatability {nx}x{ny}")
+    out = []
+    for _ in range(2):
+        p = Propagator.from_workload(w)
+        p.grad_begin(2, 4)
+        p.step(4)
+        out.append(p.grad_backward(w.w_top))
+        p.close()
+    (l1, v1, b1), (l2, v2, b2) = out
+    assert l1 == l2 and b1 == b2 and np.array_equal(v1, v2)
+
+
 def test_watchdog_and_errors():
     from paper_1903_02581_amd import Propagator, Hom4dError
     w = preset("tiny")
