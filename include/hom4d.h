@@ -116,10 +116,12 @@ size_t hom4d_state_bytes(const hom4d_cfg* cfg);
 int hom4d_bind_state(hom4d* h, void* d_psi);
 
 /* External potential V(x, y) in meV, host row-major [nx][ny] FP64, the same
- * for both electrons.  Rebuilds the potential phase tables. */
+ * for both electrons.  Rebuilds the potential phase tables and discards any
+ * gradient recording (its forward run used the old factors). */
 int hom4d_set_potential(hom4d* h, const double* v_meV);
 
-/* Change B (tesla); rebuilds the x kinetic phase tables. */
+/* Change B (tesla); rebuilds the x kinetic phase tables and discards any
+ * gradient recording. */
 int hom4d_set_field(hom4d* h, double b_tesla);
 
 /* Initial state of Sec. II.C Eq. (twopstate) from two single-electron

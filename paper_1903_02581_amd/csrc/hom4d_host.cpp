@@ -716,6 +716,7 @@ int hom4d_set_potential(hom4d* h, const double* v) {
     if (rc) return rc;
     h->have_v = true;
     h->v_hash = fnv1a(v, (size_t)c.nx * c.ny * sizeof(double));
+    h->rec = false;  // a recorded forward run used the old factors
     return HOM4D_OK;
 }
 
@@ -723,6 +724,7 @@ int hom4d_set_field(hom4d* h, double b) {
     if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
     if (!std::isfinite(b)) return fail(HOM4D_EINVAL, "B must be finite");
     h->cfg.b_tesla = b;
+    h->rec = false;  // a recorded forward run used the old factors
     return build_kinetic(h);
 }
 

@@ -273,6 +273,14 @@ def test_watchdog_and_errors():
         p.init_state(w.psi_a, w.psi_a, -1)      # antisymmetrised identical orbitals: zero norm
     with pytest.raises(Hom4dError):
         p.grad_backward(w.w_top)                 # no recording
+    for change in (lambda: p.set_field(w.b_tesla + 0.1), lambda: p.set_potential(w.v_table)):
+        p.init_state(w.psi_a, w.psi_b, -1)
+        p.grad_begin(2, 2)
+        p.step(2)
+        change()                                 # the recording used the old factors
+        with pytest.raises(Hom4dError):
+            p.grad_backward(w.w_top)
+    p.set_field(w.b_tesla)
     p.init_state(w.psi_a, w.psi_b, -1)
     p.step(3)
     p.set_norm_tol(1e-300)
