@@ -9,9 +9,15 @@ step in the oracle would not go unnoticed.
 import numpy as np
 import pytest
 
+import importlib
+
 import oracle as O
 import oracle.splitstep as SS
 from tests import test_oracle_pins as pins
+
+# the package re-exports functions named like its modules: take the modules themselves
+AD = importlib.import_module("oracle.adjoint")
+OB = importlib.import_module("oracle.observables")
 
 
 def _fails(fn, *args):
@@ -79,6 +85,41 @@ def _wrong_kappa_theta_y(g, tau):
     return (tau / g.hbar) * (1.0001 * g.kappa) * g.ky ** 2
 
 
+def _obs_tb_bt_swapped(psi, w_top):
+    o = dict(_ORIG["observables"](psi, w_top))
+    o["p_tb"], o["p_bt"] = o["p_bt"], o["p_tb"]
+    return o
+
+
+def _init_always_symmetric(psi_a, psi_b, sym):
+    return _ORIG["init_state"](psi_a, psi_b, 1 if sym == -1 else sym)
+
+
+def _entropy_in_bits(psi, ix1, jy1, ix2, jy2):
+    return _ORIG["entanglement"](psi, ix1, jy1, ix2, jy2) / np.log(2.0)
+
+
+def _attractive_coulomb(g):
+    return -_ORIG["coulomb"](g)
+
+
+def _v_full_dt_twice(psi, g, v_table, dt):
+    psi = SS.apply_x(psi, g, 0.5 * dt)
+    psi = SS.apply_v(psi, g, v_table, dt)
+    psi = SS.apply_y(psi, g, dt)
+    psi = SS.apply_v(psi, g, v_table, dt)
+    return SS.apply_x(psi, g, 0.5 * dt)
+
+
+def _dtheta_db_sign(g, tau):
+    return -_ORIG["dtheta_x_db"](g, tau)
+
+
+# unmutated functions, for the mutations that wrap them
+_ORIG = {"observables": OB.observables, "init_state": SS.init_state,
+         "entanglement": OB.entanglement, "coulomb": SS.coulomb, "dtheta_x_db": SS.dtheta_x_db}
+
+
 MUTATIONS = {
     "gauge sign (k_x + eBy/hbar)": ("theta_x", _wrong_gauge_sign, ["p2"]),
     "softening dropped from V12": ("coulomb", _dropped_coulomb_softening, ["p4"]),
@@ -87,6 +128,12 @@ MUTATIONS = {
     "kappa off by 1e-4 in T_y": ("theta_y", _wrong_kappa_theta_y, ["p1", "p2"]),
     "first-order (Lie) product": ("strang_step", _lie_step, ["p4", "p6"]),
     "X halves at full dt": ("strang_step", _x_full_twice, ["p4"]),
+    "V halves at full dt": ("strang_step", _v_full_dt_twice, ["p4"]),
+    "attractive V12": ("coulomb", _attractive_coulomb, ["p4"]),
+    "P_TB and P_BT weights swapped": ("observables", _obs_tb_bt_swapped, ["obs"]),
+    "symmetric state for sym = -1": ("init_state", _init_always_symmetric, ["p3"]),
+    "entropy in bits": ("entanglement", _entropy_in_bits, ["p8"]),
+    "d theta_X / dB with the wrong sign": ("dtheta_x_db", _dtheta_db_sign, ["p7"]),
 }
 
 
@@ -99,18 +146,28 @@ def _run_pin(name):
         return _fails(pins.test_p4_dense_expm_bruteforce, 0.0)
     if name == "p6":
         return _fails(pins.test_p6_time_reversal, _tiny_run_fixture())
+    if name == "p3":
+        return _fails(pins.test_p3_invariants_tiny, _tiny_run_fixture())
+    if name == "p7":
+        return _fails(pins.test_p7_adjoint_vs_finite_differences)
+    if name == "p8":
+        return _fails(pins.test_p8_entanglement_special_cases)
+    if name == "obs":
+        return _fails(pins.test_orbital_observables_brute_force, 0)
     raise KeyError(name)
 
 
 @pytest.mark.parametrize("label", list(MUTATIONS))
 def test_pins_catch_planted_mistake(label, monkeypatch):
     attr, fake, which = MUTATIONS[label]
-    monkeypatch.setattr(SS, attr, fake)
-    # the package re-exports; patch those names and the modules that imported them too
-    monkeypatch.setattr(O, attr, fake, raising=False)
+    # the defining module, the package's re-export and the modules that imported the name
+    for mod in (SS, OB, AD, O):
+        if hasattr(mod, attr):
+            monkeypatch.setattr(mod, attr, fake)
     caught = [p for p in which if _run_pin(p)]
     assert caught, f"no pin among {which} caught the mutation {label!r}"
 
 
 def test_pins_pass_unmutated():
-    assert not _run_pin("p2") and not _run_pin("p4")
+    for name in ("p2", "p4", "p3", "p8", "obs"):
+        assert not _run_pin(name), name

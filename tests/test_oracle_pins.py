@@ -371,3 +371,9 @@ def test_orbital_observables_brute_force(sym):
     for k, v in brute.items():
         assert abs(got[k] - v) < 1e-14, (k, got[k], v)
     assert abs(got["p_b"] - brute["p_tt"] - brute["p_bb"]) < 1e-14
+    # and the 4D region sums of observables() itself (the product state, sym = 0, has
+    # P_TB != P_BT, so a transposed weight cannot hide)
+    full = O.observables(psi, w)
+    for k, v in brute.items():
+        assert abs(full[k] - v) < 1e-14, (k, full[k], v)
+    assert abs(full["p_ab"] - brute["p_tb"] - brute["p_bt"]) < 1e-14
