@@ -14,10 +14,11 @@ probabilities (Eq. (p_bunching)) sampled every 100 steps inside the timed
 region.  value = grid-point-steps per second = (nx ny)^2 * steps / time.
 
 Extra objects on the JSON line:
-  roofline     -- the dominant pass kernel, timed with HIP events on the
-                  library's stream, against the 8 TB/s HBM peak (and, for
-                  context, against a measured 1 GiB device copy), plus the
-                  whole step's algorithmic bytes per second (step_GBps);
+  roofline     -- the dominant pass kernel, its launches timed with HIP events
+                  on the library's stream over a repeat of the timed region,
+                  against the 8 TB/s HBM peak (and, for context, against a
+                  measured 1 GiB device copy), plus the whole step's
+                  algorithmic bytes per second (step_GBps);
   cpu_baseline -- the FP64 CPU oracle on a bounded sample of the same workload;
   mixed        -- the complex64-storage form on the same workload and its error
                   against the FP64 GPU run (|dP_b|, relative L2 of psi, norm).
@@ -96,22 +97,25 @@ def timed_run(prop, w, steps, warmup, sample_every):
     return time.perf_counter() - t0, samples
 
 
-def pass_timing(prop, reps=50):
-    """Average duration of each of the four pass kernels, HIP events on the library stream."""
-    import torch
-    out = {}
-    stream = prop.stream
-    axes = (0, 4, 5) if prop.passes_per_step == 3 else (0, 1, 2, 3)
-    for axis in axes:
-        prop.run_pass(axis, 3)
-        start = torch.cuda.Event(enable_timing=True)
-        end = torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        prop.run_pass(axis, reps)
-        end.record(stream)
-        end.synchronize()
-        out[AXES[axis]] = start.elapsed_time(end) / reps * 1e-3   # seconds per launch
-    return out
+def pass_timing(prop, w, steps, sample_every):
+    """Average duration of each pass kernel over a timed region: the same number of steps
+    with the same observable sampling as the measured run, continuing its trajectory, with
+    the library bracketing every pass kernel by a HIP event pair on its own stream (kept
+    out of the run that gives the step rate, since the event records add a little time)."""
+    prop.pass_timing(True)
+    done = 0
+    while done < steps:
+        k = min(sample_every, steps - done) if sample_every else steps
+        prop.step(k)
+        done += k
+        if sample_every:
+            prop.observables(w.w_top)
+    times = prop.pass_times()
+    prop.pass_timing(False)
+    three = prop.passes_per_step == 3
+    label = {"x1": "x1", "y1": "y1+V" if three else "y1", "x2": "x2 (closing half)" if three else "x2+V",
+             "y2": "y2+V", "plane": "plane(x2,V,y2)"}
+    return {label[k]: sec / n for k, (sec, n) in times.items()}, {label[k]: n for k, (sec, n) in times.items()}
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):
@@ -279,7 +283,7 @@ def main():
         psi64_final = prop.store_state()
 
     passes_per_step = prop.passes_per_step
-    passes = pass_timing(prop)
+    passes, launches = pass_timing(prop, w, args.steps, args.sample_every)
     dom = max(passes, key=passes.get)
     sbytes = 16 if args.precision == "fp64" else 8
     alg_bytes = 2 * sbytes * P                 # one read + one write of the state per launch
@@ -294,7 +298,7 @@ def main():
         sec_m, samples_m = timed_run(pm, w, args.steps, args.warmup, args.sample_every)
         om = pm.observables(w.w_top)       # same trajectory as the FP64 run: warmup + steps
         psi_m = pm.store_state()
-        passes_m = pass_timing(pm)
+        passes_m, _ = pass_timing(pm, w, args.steps, args.sample_every)
         pm.close()
         dpb = [abs(a[1] - b[1]) for a, b in zip(samples, samples_m)]
         mixed = {
@@ -358,7 +362,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (traffic["bytes_per_launch"][dom] if traffic else None),
                      "kernel": f"pass kernel {dom}", "algorithmic_bytes_per_launch": alg_bytes,
-                     "avg_launch_s": passes[dom], "pass_seconds": passes,
+                     "avg_launch_s": passes[dom], "launches_timed": launches[dom],
+                     "pass_seconds": passes,
                      "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      # the whole step: every pass's algorithmic bytes over the timed step
                      # time (observable sampling included); a state near the 256 MB

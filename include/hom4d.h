@@ -137,6 +137,17 @@ int hom4d_init_state(hom4d* h, const double* psi_a, const double* psi_b, int32_t
 int hom4d_load_state(hom4d* h, const double* psi4d);
 int hom4d_store_state(hom4d* h, double* psi4d);
 
+/* Measurement: per-pass kernel timing on the stream.  enable = 1 discards
+ * earlier records and brackets every pass kernel launched afterwards by a HIP
+ * event pair; 0 stops recording.  hom4d_pass_times synchronises and returns,
+ * per pass kind (0 x1, 1 y1, 2 x2, 3 y2, 4 the fused (x2, y2) plane pass), the
+ * summed event-to-event time in ms and the number of launches (host arrays of
+ * 5).  Events are created as needed and kept until hom4d_destroy.  The event
+ * records add a little time between kernels, so a run that measures the step
+ * rate leaves timing off. */
+int hom4d_pass_timing(hom4d* h, int32_t enable);
+int hom4d_pass_times(hom4d* h, double* ms, int64_t* count);
+
 /* Checkpoint images for resuming a long run (not an operation of the paper:
  * its propagations take thousands of steps, Sec. III).  An image is a 64-byte
  * header -- magic "HOM4DCK1", version 1, precision, nx, ny, step count, a

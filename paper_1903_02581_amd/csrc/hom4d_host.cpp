@@ -225,9 +225,42 @@ struct hom4d {
     int64_t rec_steps = 0;
     double* g_buf = nullptr;     // all gradient partials
     size_t g_len = 0;
+    // pass timing (measurement): an event pair around every pass kernel launch
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pool, 2 per recorded launch
+    std::vector<int> ev_kind;    // pass kind of each recorded launch (0..4)
 };
 
 namespace {
+
+void free_events(hom4d* h) {
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    h->ev.clear();
+    h->ev_kind.clear();
+}
+
+// Launch one pass kernel; while timing is on, between an event pair of its own.
+// kind: 0 x1, 1 y1, 2 x2, 3 y2 (the axis), 4 the fused plane pass.
+template <class F>
+hipError_t timed_launch(hom4d* h, int kind, F&& launch) {
+    if (!h->timing) return launch();
+    const size_t i = 2 * h->ev_kind.size();
+    while (h->ev.size() < i + 2) {
+        const size_t grow = h->ev.empty() ? 4096 : h->ev.size();
+        for (size_t k = 0; k < grow; ++k) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            h->ev.push_back(e);
+        }
+    }
+    hipError_t err = hipEventRecord(h->ev[i], h->stream);
+    if (err != hipSuccess) return err;
+    if ((err = launch()) != hipSuccess) return err;
+    if ((err = hipEventRecord(h->ev[i + 1], h->stream)) != hipSuccess) return err;
+    h->ev_kind.push_back(kind);
+    return hipSuccess;
+}
 
 int upload(hom4d* h, void* dst, const void* src, size_t bytes) {
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
@@ -368,7 +401,7 @@ int run_pass(hom4d* h, int axis, KTab kt, int vmode, int nst, void* lam, bool re
         if (axis == AX_Y2) { a.marg_part = g->m_y2; }
     }
     if (vmode && !h->have_v) return fail(HOM4D_ESTATE, "no potential set (hom4d_set_potential)");
-    HIP_TRY(launch_axis(axis, p.n, h->mixed, nst, a, p.nlines, p.lds, h->stream));
+    HIP_TRY(timed_launch(h, axis, [&] { return launch_axis(axis, p.n, h->mixed, nst, a, p.nlines, p.lds, h->stream); }));
     return sync_check(h, "axis pass");
 }
 
@@ -394,7 +427,7 @@ int run_plane(hom4d* h, KTab kt) {
     a.soft2 = c.soft_nm * c.soft_nm;
     a.ck = c.coulomb_c * h->u.kc;
     a.inv_screen = c.screen_nm > 0.0 ? 1.0 / c.screen_nm : 0.0;
-    HIP_TRY(launch_plane(c.nx, c.ny, h->mixed, a, h->stream));
+    HIP_TRY(timed_launch(h, 4, [&] { return launch_plane(c.nx, c.ny, h->mixed, a, h->stream); }));
     return sync_check(h, "plane pass");
 }
 
@@ -685,6 +718,7 @@ int hom4d_create(const hom4d_cfg* cfg, void* hip_stream, hom4d** out) {
 int hom4d_destroy(hom4d* h) {
     if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_events(h);
     free_all(h);
     delete h;
     return HOM4D_OK;
@@ -1090,6 +1124,34 @@ int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs, voi
     *loss = L;
     h->step -= h->rec_steps;
     h->rec = false;
+    return HOM4D_OK;
+}
+
+int hom4d_pass_timing(hom4d* h, int32_t enable) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (enable != 0 && enable != 1) return fail(HOM4D_EINVAL, "enable=%d must be 0 or 1", enable);
+    if (enable) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->ev_kind.clear();  // the pool of events is kept
+    }
+    h->timing = enable == 1;
+    return HOM4D_OK;
+}
+
+int hom4d_pass_times(hom4d* h, double* ms, int64_t* count) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!ms || !count) return fail(HOM4D_EINVAL, "NULL argument");
+    for (int k = 0; k < 5; ++k) {
+        ms[k] = 0.0;
+        count[k] = 0;
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (size_t i = 0; i < h->ev_kind.size(); ++i) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, h->ev[2 * i], h->ev[2 * i + 1]));
+        ms[h->ev_kind[i]] += t;
+        count[h->ev_kind[i]] += 1;
+    }
     return HOM4D_OK;
 }
 

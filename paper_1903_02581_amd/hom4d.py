@@ -33,7 +33,7 @@ EXPORTS = ["hom4d_create", "hom4d_destroy", "hom4d_validate_cfg", "hom4d_state_b
            "hom4d_set_norm_tol", "hom4d_entanglement", "hom4d_gather_slice", "hom4d_marginal",
            "hom4d_conditional", "hom4d_grad_begin",
            "hom4d_grad_backward", "hom4d_grad_end", "hom4d_run_pass", "hom4d_set_pass_plan",
-           "hom4d_pass_plan", "hom4d_strerror",
+           "hom4d_pass_plan", "hom4d_pass_timing", "hom4d_pass_times", "hom4d_strerror",
            "hom4d_last_error"]
 
 
@@ -97,6 +97,8 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "hom4d_run_pass": ([vp, c_int32, c_int32], c_int),
         "hom4d_set_pass_plan": ([vp, c_int32], c_int),
         "hom4d_pass_plan": ([vp], c_int),
+        "hom4d_pass_timing": ([vp, c_int32], c_int),
+        "hom4d_pass_times": ([vp, dp, POINTER(c_int64)], c_int),
         "hom4d_strerror": ([c_int], ctypes.c_char_p),
         "hom4d_last_error": ([], ctypes.c_char_p),
     }
@@ -319,6 +321,20 @@ class Propagator:
         if rc < 0:
             self._check(rc, "pass_plan")
         return int(rc)
+
+    PASS_KINDS = ("x1", "y1", "x2", "y2", "plane")
+
+    def pass_timing(self, enable: bool):
+        """Bracket every pass kernel launched from now on by a HIP event pair (measurement)."""
+        self._check(self.lib.hom4d_pass_timing(self.h, 1 if enable else 0), "pass_timing")
+
+    def pass_times(self) -> dict:
+        """{kind: (summed seconds, launches)} of the launches recorded since pass_timing(True)."""
+        ms = np.zeros(5, dtype=np.float64)
+        cnt = np.zeros(5, dtype=np.int64)
+        self._check(self.lib.hom4d_pass_times(self.h, _dptr(ms), cnt.ctypes.data_as(POINTER(c_int64))),
+                    "pass_times")
+        return {k: (float(ms[i]) * 1e-3, int(cnt[i])) for i, k in enumerate(self.PASS_KINDS) if cnt[i]}
 
     def run_pass(self, axis: int, reps: int = 1):
         """Launch one of the four fused pass kernels reps times (measurement only)."""
