@@ -283,7 +283,7 @@ hipError_t launch_plane(int nx, int ny, bool mixed, const PassArgs& a, hipStream
     int nt = 0;
     const int vk = a.vdirect ? 2 : 1;
     AxisKernel fn = mixed ? pick_plane_f32(nx, ny, vk, &nt) : pick_plane_f64(nx, ny, vk, &nt);
-    if (!fn || nt <= 0 || nt > 512) return hipErrorInvalidValue;
+    if (!fn || nt <= 0 || nt > 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)(nx * ny)), dim3(nt), 0, s, a);
     return hipGetLastError();
 }

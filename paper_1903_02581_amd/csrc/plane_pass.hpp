@@ -58,12 +58,16 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
     using LY = PlaneLds<NY>;
     constexpr int A1 = SX_::n1, A2 = SX_::n2, TX = SX_::t;
     constexpr int B1 = SY_::n1, B2 = SY_::n2, TY = SY_::t;
-    constexpr int EX = NX / TX, EY = NY / TY;
+    constexpr int EX = NX / TX;
     constexpr int JAX = A2 / TX, IBX = A1 / TX;
     constexpr int JAY = B2 / TY, IBY = B1 / TY;
     constexpr int SLX = NY * TX, QX = (SLX + NT - 1) / NT;
     constexpr int SLY = NX * TY, QY = (SLY + NT - 1) / NT;
     using X = Xchg<S>;
+    // Where the potential factor is applied: at the end of the X2 stage (FP64
+    // storage) or as the Y2 stage reads its rows (complex64 storage, where the
+    // smaller register footprint buys a resident wavefront per SIMD).
+    constexpr bool V_IN_Y = !std::is_same<S, double2>::value;
     __shared__ typename X::T L[NX * LY::row];
     __shared__ double2 TW[NX + 2 * NY];  // x twiddles, y twiddles, y kinetic factor
 
@@ -218,14 +222,16 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                     }
                     dft<A1, 1>(&vb[q][jj * A1]);
                 }
-                // potential factor in real space at (x2 = n1 * A2 + t + TX * jj, y2 = c)
+                if constexpr (!V_IN_Y) {
+                    // potential factor in real space at (x2 = n1 * A2 + t + TX * jj, y2 = c)
 #pragma unroll
-                for (int jj = 0; jj < JAX; ++jj)
+                    for (int jj = 0; jj < JAX; ++jj)
 #pragma unroll
-                    for (int n1 = 0; n1 < A1; ++n1) {
-                        const double2 f = vfactor<VK == 1 ? 3 : VK>(av, i1, j1, n1 * A2 + t + TX * jj, c);
-                        vb[q][jj * A1 + n1] = cmul(vb[q][jj * A1 + n1], f);
-                    }
+                        for (int n1 = 0; n1 < A1; ++n1) {
+                            const double2 f = vfactor<VK == 1 ? 3 : VK>(av, i1, j1, n1 * A2 + t + TX * jj, c);
+                            vb[q][jj * A1 + n1] = cmul(vb[q][jj * A1 + n1], f);
+                        }
+                }
             }
         }
 #pragma unroll
@@ -247,6 +253,9 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
         // from moving or forwarding LDS accesses across the wait); no workgroup
         // barrier.  (The column exchanges of the X2 stage span wavefronts: a
         // column-per-wavefront thread mapping measured slower, 127 -> 150 us.)
+        // Each sub-transform reads and writes back the same LDS slots, so the
+        // stages take one sub-transform at a time and hold only its values in
+        // registers.
         constexpr bool Y_WAVE = (QY == 1) && (64 % TY == 0);
         auto y_sync = [&]() {
             if constexpr (Y_WAVE)
@@ -254,126 +263,105 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
             else
                 __syncthreads();
         };
-        double2 vy[QY][EY];
-#pragma unroll
-        for (int q = 0; q < QY; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLY) {
-                const int t = s % TY, row = s / TY;
-#pragma unroll
-                for (int jj = 0; jj < JAY; ++jj)
-#pragma unroll
-                    for (int n1 = 0; n1 < B1; ++n1) vy[q][jj * B1 + n1] = X::get(L[LY::at(row, n1 * B2 + t + TY * jj)]);
-#pragma unroll
-                for (int jj = 0; jj < JAY; ++jj) {
-                    dft<B1, -1>(&vy[q][jj * B1]);
-                    if constexpr (B2 > 1) {
-                        const int jc = t + TY * jj;
-#pragma unroll
-                        for (int k1 = 1; k1 < B1; ++k1)
-                            vy[q][jj * B1 + k1] = cmul(vy[q][jj * B1 + k1], twy[(jc * k1) % NY]);
-                    }
-                }
-            }
-        }
         if constexpr (B2 > 1) {
+            // stage A: DFT_B1 and twiddles, in place
 #pragma unroll
             for (int q = 0; q < QY; ++q) {
                 const int s = tid + NT * q;
                 if (s < SLY) {
                     const int t = s % TY, row = s / TY;
 #pragma unroll
-                    for (int jj = 0; jj < JAY; ++jj)
+                    for (int jj = 0; jj < JAY; ++jj) {
+                        double2 u[B1];
 #pragma unroll
-                        for (int k1 = 0; k1 < B1; ++k1) L[LY::at(row, k1 * B2 + t + TY * jj)] = X::put(vy[q][jj * B1 + k1]);
+                        for (int n1 = 0; n1 < B1; ++n1) u[n1] = X::get(L[LY::at(row, n1 * B2 + t + TY * jj)]);
+                        if constexpr (V_IN_Y) {
+                            // potential factor in real space at (x2 = row, y2)
+#pragma unroll
+                            for (int n1 = 0; n1 < B1; ++n1)
+                                u[n1] = cmul(u[n1], vfactor<VK == 1 ? 3 : VK>(av, i1, j1, row, n1 * B2 + t + TY * jj));
+                        }
+                        dft<B1, -1>(u);
+                        const int jc = t + TY * jj;
+#pragma unroll
+                        for (int k1 = 1; k1 < B1; ++k1) u[k1] = cmul(u[k1], twy[(jc * k1) % NY]);
+#pragma unroll
+                        for (int k1 = 0; k1 < B1; ++k1) L[LY::at(row, k1 * B2 + t + TY * jj)] = X::put(u[k1]);
+                    }
                 }
             }
             y_sync();
+            // stage B: DFT_B2, kinetic y phase, inverse DFT_B2, in place
 #pragma unroll
             for (int q = 0; q < QY; ++q) {
                 const int s = tid + NT * q;
                 if (s < SLY) {
                     const int t = s % TY, row = s / TY;
 #pragma unroll
-                    for (int ii = 0; ii < IBY; ++ii)
+                    for (int ii = 0; ii < IBY; ++ii) {
+                        double2 u[B2];
 #pragma unroll
-                        for (int j = 0; j < B2; ++j) vy[q][ii * B2 + j] = X::get(L[LY::at(row, (t + TY * ii) * B2 + j)]);
+                        for (int j = 0; j < B2; ++j) u[j] = X::get(L[LY::at(row, (t + TY * ii) * B2 + j)]);
+                        dft<B2, -1>(u);
 #pragma unroll
-                    for (int ii = 0; ii < IBY; ++ii) dft<B2, -1>(&vy[q][ii * B2]);
-                }
-            }
-        }
+                        for (int k2 = 0; k2 < B2; ++k2) u[k2] = cmul(u[k2], ky[t + TY * ii + B1 * k2]);
+                        dft<B2, 1>(u);
 #pragma unroll
-        for (int q = 0; q < QY; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLY) {
-                const int t = s % TY;
-#pragma unroll
-                for (int ii = 0; ii < IBY; ++ii)
-#pragma unroll
-                    for (int k2 = 0; k2 < B2; ++k2) {
-                        vy[q][ii * B2 + k2] = cmul(vy[q][ii * B2 + k2], ky[t + TY * ii + B1 * k2]);
+                        for (int j = 0; j < B2; ++j) L[LY::at(row, (t + TY * ii) * B2 + j)] = X::put(u[j]);
                     }
-                if constexpr (B2 > 1) {
-#pragma unroll
-                    for (int ii = 0; ii < IBY; ++ii) dft<B2, 1>(&vy[q][ii * B2]);
-                }
-            }
-        }
-        if constexpr (B2 > 1) {
-#pragma unroll
-            for (int q = 0; q < QY; ++q) {
-                const int s = tid + NT * q;
-                if (s < SLY) {
-                    const int t = s % TY, row = s / TY;
-#pragma unroll
-                    for (int ii = 0; ii < IBY; ++ii)
-#pragma unroll
-                        for (int j = 0; j < B2; ++j) L[LY::at(row, (t + TY * ii) * B2 + j)] = X::put(vy[q][ii * B2 + j]);
                 }
             }
             y_sync();
+            // stage A inverse: conjugate twiddles, inverse DFT_B1, store
 #pragma unroll
             for (int q = 0; q < QY; ++q) {
                 const int s = tid + NT * q;
                 if (s < SLY) {
                     const int t = s % TY, row = s / TY;
 #pragma unroll
-                    for (int jj = 0; jj < JAY; ++jj)
+                    for (int jj = 0; jj < JAY; ++jj) {
+                        double2 u[B1];
 #pragma unroll
-                        for (int k1 = 0; k1 < B1; ++k1) vy[q][jj * B1 + k1] = X::get(L[LY::at(row, k1 * B2 + t + TY * jj)]);
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < QY; ++q) {
-            const int s = tid + NT * q;
-            if (s < SLY) {
-                const int t = s % TY, row = s / TY;
-#pragma unroll
-                for (int jj = 0; jj < JAY; ++jj) {
-                    if constexpr (B2 > 1) {
+                        for (int k1 = 0; k1 < B1; ++k1) u[k1] = X::get(L[LY::at(row, k1 * B2 + t + TY * jj)]);
                         const int jc = t + TY * jj;
 #pragma unroll
-                        for (int k1 = 1; k1 < B1; ++k1)
-                            vy[q][jj * B1 + k1] = cmulc(vy[q][jj * B1 + k1], twy[(jc * k1) % NY]);
+                        for (int k1 = 1; k1 < B1; ++k1) u[k1] = cmulc(u[k1], twy[(jc * k1) % NY]);
+                        dft<B1, 1>(u);
+#pragma unroll
+                        for (int n1 = 0; n1 < B1; ++n1) st<S>(base + row * NY + n1 * B2 + t + TY * jj, u[n1]);
                     }
-                    dft<B1, 1>(&vy[q][jj * B1]);
                 }
+            }
+        } else {
+            // a whole row per thread: DFT, kinetic y phase, inverse DFT
 #pragma unroll
-                for (int jj = 0; jj < JAY; ++jj)
+            for (int q = 0; q < QY; ++q) {
+                const int s = tid + NT * q;
+                if (s < SLY) {
+                    const int row = s / TY;
+                    double2 u[B1];
 #pragma unroll
-                    for (int n1 = 0; n1 < B1; ++n1) st<S>(base + row * NY + n1 * B2 + t + TY * jj, vy[q][jj * B1 + n1]);
+                    for (int n1 = 0; n1 < B1; ++n1) {
+                        u[n1] = X::get(L[LY::at(row, n1)]);
+                        if constexpr (V_IN_Y) u[n1] = cmul(u[n1], vfactor<VK == 1 ? 3 : VK>(av, i1, j1, row, n1));
+                    }
+                    dft<B1, -1>(u);
+#pragma unroll
+                    for (int k1 = 0; k1 < B1; ++k1) u[k1] = cmul(u[k1], ky[k1]);
+                    dft<B1, 1>(u);
+#pragma unroll
+                    for (int n1 = 0; n1 < B1; ++n1) st<S>(base + row * NY + n1, u[n1]);
+                }
             }
         }
     }
 }
 
-// Threads per plane workgroup: enough for the larger of the two stages, at most 512.
+// Threads per plane workgroup: enough for the larger of the two stages, at most 1024.
 constexpr int plane_threads(int nx, int ny, int tx, int ty) {
     const int s = (ny * tx > nx * ty) ? ny * tx : nx * ty;
     const int r = ((s + 63) / 64) * 64;
-    return r > 512 ? 512 : r;
+    return r > 1024 ? 1024 : r;
 }
 
 }  // namespace dev
