@@ -223,8 +223,7 @@ REPEAT_SIZES = SIZES + [(16, 16), (24, 24), (32, 32), (48, 48), (64, 64), (48, 1
 def test_bitwise_repeatable_every_size(precision):
     from paper_1903_02581_amd import Propagator
     announce(f"bitwise repeatability, {len(REPEAT_SIZES)} shapes, {precision}")
-    # 128x96 has a fused plane kernel in complex64 storage only
-    for nx, ny in REPEAT_SIZES + ([(128, 96)] if precision == "mixed" else []):
+    for nx, ny in REPEAT_SIZES:
         w = build("rep", nx, ny, 10.0 * nx, 12.0 * ny, b_tesla=5.0, dt_fs=2.0, steps=3,
                   sigma_x=max(10.0, 2.0 * nx), seed=nx * ny)
         runs = []

@@ -66,24 +66,3 @@ def test_three_pass_mixed_and_direct(mode, nx, ny, steps):
     assert rel_l2(res["fp64"], ref4) <= 1e-13
     assert rel_l2(res["mixed"], ref4) <= 1e-4
 
-
-@pytest.mark.parametrize("mode", ["table", "direct"])
-def test_three_pass_complex64_128x96(mode):
-    """The complex64 plane kernel at 128x96 (one 768-thread workgroup per compute unit; no
-    FP64 plane kernel at this size): against the complex64 and FP64 per-axis steps."""
-    from paper_1903_02581_amd import Propagator
-    w = _w(128, 96, 4)
-    announce(f"plane complex64/{mode} 128x96 steps={w.steps}")
-    out = {}
-    for prec, plan in (("mixed", 0), ("mixed", 1), ("fp64", 0)):
-        p = Propagator.from_workload(w, precision=prec, coulomb_mode=mode)
-        p.set_pass_plan(plan)
-        assert p.passes_per_step == (3 if (prec, plan) == ("mixed", 0) else 4)
-        p.step(w.steps)
-        out[(prec, plan)] = p.store_state()
-        p.close()
-    m3, m4, f64 = out[("mixed", 0)], out[("mixed", 1)], out[("fp64", 0)]
-    # both complex64 forms carry only rounding differences (a few roundings of 6e-8 per pass)
-    assert rel_l2(m3, m4) <= 1e-5
-    assert rel_l2(m3, f64) <= 1e-5
-    assert rel_l2(m4, f64) <= 1e-5
