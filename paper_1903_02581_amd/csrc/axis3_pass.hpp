@@ -5,7 +5,8 @@
 // thread holds 8 (or 12) elements instead of 16 (or 24) and the kernels keep
 // enough waves resident to stream HBM.  n = 256 takes 32 threads per line, so
 // its blocks hold 16 lines in 512 threads (128-byte runs on the strided axes
-// in complex64 storage).
+// in complex64 storage), or 32 lines in 1024 threads on the complex64 x1 and
+// y1 passes.
 //
 // Line of n = R1 R2 R3 points, element m = n1 (R2 R3) + n2 R3 + j3, handled by T
 // threads.  Forward:
@@ -41,7 +42,7 @@ struct Net3 {
 };
 
 template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK>
-__global__ void __launch_bounds__(512) k_axis3(const PassArgs a) {
+__global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !std::is_same<S, double2>::value)) k_axis3(const PassArgs a) {
     using NT = Net3<R1, R2, R3, T>;
     constexpr int N = NT::N, N2 = NT::N2, JA = NT::JA, G1 = NT::G1, G2 = NT::G2, E = NT::E;
     using X = Xchg<S>;

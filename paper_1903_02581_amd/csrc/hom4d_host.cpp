@@ -132,12 +132,18 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         // factors.  n = 128: 16 lines (256 threads) within 48 KB, so that three
         // or more blocks share a CU; n = 96 and 256 measured faster with wider
         // blocks: 32 lines (256 threads) and 16 lines (512 threads) within 80 KB
-        // The reverse sweep's dual-state blocks take two exchange areas within
-        // 80 KB, counted in the storage's entry size.
+        // (in complex128 entries).  The complex64 x1 and y1 passes at n = 256
+        // take 32 lines (1024 threads; complex64 entries, within 80 KB): x1
+        // 7.12 -> 6.70 ms, y1 4.60 -> 4.52-4.59 ms at 256 x 128, while the x2
+        // pass measured slower (6.72 -> 7.97 ms) and y2 unchanged that way.  The reverse sweep's
+        // dual-state blocks take two exchange areas within 80 KB, counted in
+        // the storage's entry size.
         p.t = t3;
         const bool wide = p.n != 128;
-        int64_t w = (wide ? 512 : 256) / t3;
-        const int64_t cap = nst == 1 ? ((wide ? 81920 : 49152) - 2 * p.n * 16) / ((int64_t)p.n * 16) - 1
+        const int bt = axis3_block_threads(axis, p.n, nst, mixed);
+        int64_t w = (bt == 1024 ? 1024 : wide ? 512 : 256) / t3;
+        const int64_t cap = bt == 1024 ? (81920 - 2 * p.n * 16) / ((int64_t)p.n * 8) - 1
+                          : nst == 1 ? ((wide ? 81920 : 49152) - 2 * p.n * 16) / ((int64_t)p.n * 16) - 1
                                      : (81920 - 2 * p.n * 16) / ((int64_t)2 * p.n * (mixed ? 8 : 16)) - 1;
         while (w > cap) w >>= 1;
         w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));

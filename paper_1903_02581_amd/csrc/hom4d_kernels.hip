@@ -248,7 +248,7 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
         fn = (nst == 2) ? pick_axis_f32_2(axis, n, vk, &t) : pick_axis_f32_1(axis, n, vk, &t);
     if (!fn || a.W <= 0 || nlines % a.W != 0) return hipErrorInvalidValue;
     const int64_t nblocks = nlines / a.W;
-    const int max_threads = axis3_threads(n, nst) > 0 ? 512 : 256;
+    const int max_threads = axis3_threads(n, nst) > 0 ? axis3_block_threads(axis, n, nst, mixed) : 256;
     if (nblocks > 0x7fffffff || t * a.W > max_threads || lds_bytes > 160 * 1024) return hipErrorInvalidValue;
     if (axis3_threads(n, nst) > 0) {
         if (lds_bytes < axis3_lds_bytes(n, a.W, nst, mixed)) return hipErrorInvalidValue;

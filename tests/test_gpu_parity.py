@@ -46,7 +46,7 @@ def test_sizes_fp64(nx, ny):
     assert rel_l2(psi, ref) <= FP64_TOL
 
 
-@pytest.mark.parametrize("nx,ny", [(16, 16), (48, 16), (16, 96)])
+@pytest.mark.parametrize("nx,ny", [(16, 16), (48, 16), (16, 96), (256, 8), (8, 256), (128, 12)])
 def test_sizes_mixed(nx, ny):
     w = build("szm", nx, ny, 10.0 * nx, 12.0 * ny, b_tesla=5.0, dt_fs=2.0, steps=20,
               sigma_x=20.0, seed=3)
