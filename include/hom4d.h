@@ -142,7 +142,10 @@ int hom4d_store_state(hom4d* h, double* psi4d);
  * event pair; 0 stops recording.  hom4d_pass_times synchronises and returns,
  * per pass kind (0 x1, 1 y1, 2 x2, 3 y2, 4 the fused (x2, y2) plane pass), the
  * summed event-to-event time in ms and the number of launches (host arrays of
- * 5).  Events are created as needed and kept until hom4d_destroy.  The event
+ * 5); reading does not reset them.  A pool of 8192 events is created at the
+ * first timed launch and kept until hom4d_destroy: while timing is on, every
+ * 4096 launches the stream is synchronised and the pending pairs are folded
+ * into the sums, so memory stays bounded over any number of steps.  The event
  * records add a little time between kernels, so a run that measures the step
  * rate leaves timing off. */
 int hom4d_pass_timing(hom4d* h, int32_t enable);

@@ -233,8 +233,10 @@ struct hom4d {
     size_t g_len = 0;
     // pass timing (measurement): an event pair around every pass kernel launch
     bool timing = false;
-    std::vector<hipEvent_t> ev;  // pool, 2 per recorded launch
-    std::vector<int> ev_kind;    // pass kind of each recorded launch (0..4)
+    std::vector<hipEvent_t> ev;  // pool of 2 * kEvPairs events, created at the first timed launch
+    std::vector<int> ev_kind;    // pass kind of each pending pair (0..4)
+    double ev_ms[5] = {};        // folded sums per kind
+    int64_t ev_n[5] = {};
 };
 
 namespace {
@@ -245,22 +247,40 @@ void free_events(hom4d* h) {
     h->ev_kind.clear();
 }
 
+constexpr size_t kEvPairs = 4096;
+
+// Wait for the pending event pairs and add their times to the per-kind sums;
+// the events are then free for reuse.
+hipError_t fold_events(hom4d* h) {
+    if (h->ev_kind.empty()) return hipSuccess;
+    hipError_t err = hipStreamSynchronize(h->stream);
+    if (err != hipSuccess) return err;
+    for (size_t i = 0; i < h->ev_kind.size(); ++i) {
+        float t = 0.0f;
+        if ((err = hipEventElapsedTime(&t, h->ev[2 * i], h->ev[2 * i + 1])) != hipSuccess) return err;
+        h->ev_ms[h->ev_kind[i]] += t;
+        h->ev_n[h->ev_kind[i]] += 1;
+    }
+    h->ev_kind.clear();
+    return hipSuccess;
+}
+
 // Launch one pass kernel; while timing is on, between an event pair of its own.
-// kind: 0 x1, 1 y1, 2 x2, 3 y2 (the axis), 4 the fused plane pass.
+// kind: 0 x1, 1 y1, 2 x2, 3 y2 (the axis), 4 the fused plane pass.  The pool
+// holds kEvPairs pairs; when they are all pending the stream is synchronised
+// and their times folded into the sums.
 template <class F>
 hipError_t timed_launch(hom4d* h, int kind, F&& launch) {
     if (!h->timing) return launch();
-    const size_t i = 2 * h->ev_kind.size();
-    while (h->ev.size() < i + 2) {
-        const size_t grow = h->ev.empty() ? 4096 : h->ev.size();
-        for (size_t k = 0; k < grow; ++k) {
-            hipEvent_t e;
-            hipError_t err = hipEventCreate(&e);
-            if (err != hipSuccess) return err;
-            h->ev.push_back(e);
-        }
+    hipError_t err;
+    while (h->ev.size() < 2 * kEvPairs) {
+        hipEvent_t e;
+        if ((err = hipEventCreate(&e)) != hipSuccess) return err;
+        h->ev.push_back(e);
     }
-    hipError_t err = hipEventRecord(h->ev[i], h->stream);
+    if (h->ev_kind.size() == kEvPairs && (err = fold_events(h)) != hipSuccess) return err;
+    const size_t i = 2 * h->ev_kind.size();
+    err = hipEventRecord(h->ev[i], h->stream);
     if (err != hipSuccess) return err;
     if ((err = launch()) != hipSuccess) return err;
     if ((err = hipEventRecord(h->ev[i + 1], h->stream)) != hipSuccess) return err;
@@ -1139,6 +1159,10 @@ int hom4d_pass_timing(hom4d* h, int32_t enable) {
     if (enable) {
         HIP_TRY(hipStreamSynchronize(h->stream));
         h->ev_kind.clear();  // the pool of events is kept
+        for (int k = 0; k < 5; ++k) {
+            h->ev_ms[k] = 0.0;
+            h->ev_n[k] = 0;
+        }
     }
     h->timing = enable == 1;
     return HOM4D_OK;
@@ -1147,16 +1171,11 @@ int hom4d_pass_timing(hom4d* h, int32_t enable) {
 int hom4d_pass_times(hom4d* h, double* ms, int64_t* count) {
     if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
     if (!ms || !count) return fail(HOM4D_EINVAL, "NULL argument");
-    for (int k = 0; k < 5; ++k) {
-        ms[k] = 0.0;
-        count[k] = 0;
-    }
     HIP_TRY(hipStreamSynchronize(h->stream));
-    for (size_t i = 0; i < h->ev_kind.size(); ++i) {
-        float t = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&t, h->ev[2 * i], h->ev[2 * i + 1]));
-        ms[h->ev_kind[i]] += t;
-        count[h->ev_kind[i]] += 1;
+    HIP_TRY(fold_events(h));
+    for (int k = 0; k < 5; ++k) {
+        ms[k] = h->ev_ms[k];
+        count[k] = h->ev_n[k];
     }
     return HOM4D_OK;
 }
