@@ -5,8 +5,8 @@
 // thread holds 8 (or 12) elements instead of 16 (or 24) and the kernels keep
 // enough waves resident to stream HBM.  n = 256 takes 32 threads per line, so
 // its blocks hold 16 lines in 512 threads (128-byte runs on the strided axes
-// in complex64 storage), or 32 lines in 1024 threads on the complex64 x1 and
-// y1 passes.
+// in complex64 storage), or 32 lines in 1024 threads on the complex64 x1
+// pass.
 //
 // Line of n = R1 R2 R3 points, element m = n1 (R2 R3) + n2 R3 + j3, handled by T
 // threads.  Forward:

@@ -132,10 +132,10 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         // factors.  n = 128: 16 lines (256 threads) within 48 KB, so that three
         // or more blocks share a CU; n = 96 and 256 measured faster with wider
         // blocks: 32 lines (256 threads) and 16 lines (512 threads) within 80 KB
-        // (in complex128 entries).  The complex64 x1 and y1 passes at n = 256
-        // take 32 lines (1024 threads; complex64 entries, within 80 KB): x1
-        // 7.12 -> 6.70 ms, y1 4.60 -> 4.52-4.59 ms at 256 x 128, while the x2
-        // pass measured slower (6.72 -> 7.97 ms) and y2 unchanged that way.  The reverse sweep's
+        // (in complex128 entries).  The complex64 x1 pass at n = 256 takes 32
+        // lines (1024 threads; complex64 entries, within 80 KB): 7.12 -> 6.70 ms
+        // at 256 x 128, while the x2 pass measured slower that way (6.72 ->
+        // 7.97 ms).  The reverse sweep's
         // dual-state blocks take two exchange areas within 80 KB, counted in
         // the storage's entry size.
         p.t = t3;

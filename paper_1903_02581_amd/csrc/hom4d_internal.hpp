@@ -61,10 +61,10 @@ bool fft_shape(int n, FftShape* out);
 int axis3_threads(int n, int nst);
 
 // Threads per block of the three-stage kernel: 1024 for the complex64 forward
-// x1 and y1 passes at n = 256 (32 lines of 32 threads: 256-byte runs on these
-// strided axes), 512 otherwise.
+// x1 pass at n = 256 (32 lines of 32 threads: 256-byte runs on its strided
+// axis), 512 otherwise.
 __host__ __device__ constexpr int axis3_block_threads(int axis, int n, int nst, bool mixed) {
-    return (n == 256 && nst == 1 && mixed && (axis == AX_X1 || axis == AX_Y1)) ? 1024 : 512;
+    return (n == 256 && nst == 1 && mixed && axis == AX_X1) ? 1024 : 512;
 }
 
 // Whether the two-stage kernel's exchanges on this axis are complex64 (with
