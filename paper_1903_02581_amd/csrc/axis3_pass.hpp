@@ -41,10 +41,10 @@ struct Net3 {
     static_assert(G1 * R2 == E && G2 * R3 == E, "every stage must give a thread E elements");
 };
 
-template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK>
+template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT>
 __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !std::is_same<S, double2>::value)) k_axis3(const PassArgs a) {
-    using NT = Net3<R1, R2, R3, T>;
-    constexpr int N = NT::N, N2 = NT::N2, JA = NT::JA, G1 = NT::G1, G2 = NT::G2, E = NT::E;
+    using NW = Net3<R1, R2, R3, T>;
+    constexpr int N = NW::N, N2 = NW::N2, JA = NW::JA, G1 = NW::G1, G2 = NW::G2, E = NW::E;
     using X = Xchg<S>;
     extern __shared__ double2 lds_raw[];
 
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
             for (int n1 = 0; n1 < R1; ++n1)
-                v[s][jj * R1 + n1] = ld<S>(ps[s] + (int64_t)(n1 * N2 + t + T * jj) * lg.sN);
+                v[s][jj * R1 + n1] = ld<S, NT>(ps[s] + (int64_t)(n1 * N2 + t + T * jj) * lg.sN);
 
     // gradient accumulators of the reverse sweep: the potential marginal
     // Im(conj(lambda) psi) on the side of the potential factor the pass is told
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
             for (int n1 = 0; n1 < R1; ++n1)
-                st<S>(ps[s] + (int64_t)(n1 * N2 + t + T * jj) * lg.sN, v[s][jj * R1 + n1]);
+                st<S, NT>(ps[s] + (int64_t)(n1 * N2 + t + T * jj) * lg.sN, v[s][jj * R1 + n1]);
 
     if constexpr (NST == 2) {
         // the same partial-sum layout as the two-stage pass: dL/dB per block; the
@@ -285,12 +285,12 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
 }
 
 // Three-stage factorisations: n = R1 R2 R3 on T threads per line.
-template <class S, int AXIS, int NST, int VK>
+template <class S, int AXIS, int NST, int VK, bool NT>
 AxisKernel pick3(int n, int* t) {
     switch (n) {
-        case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, NST, VK>;
-        case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, NST, VK>;
-        case 256: *t = 32; return k_axis3<S, AXIS, 8, 8, 4, 32, NST, VK>;
+        case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, NST, VK, NT>;
+        case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, NST, VK, NT>;
+        case 256: *t = 32; return k_axis3<S, AXIS, 8, 8, 4, 32, NST, VK, NT>;
         default: *t = 0; return nullptr;
     }
 }
@@ -298,23 +298,23 @@ AxisKernel pick3(int n, int* t) {
 // Forward single-state passes: the x1 pass carries no potential factor, the
 // y2 pass always carries it, x2 and y1 either.  Reverse dual-state passes: the
 // x passes carry none, y1 (before its transform) and y2 (after) carry it.
-template <class S>
-AxisKernel pick_axis3(int axis, int n, int vk, int nst, int* t) {
+template <class S, bool NT>
+AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, int* t) {
     if (nst == 2) {
         switch (axis) {
             case AX_X1:
-                if (vk == 0) return pick3<S, AX_X1, 2, 0>(n, t);
+                if (vk == 0) return pick3<S, AX_X1, 2, 0, NT>(n, t);
                 break;
             case AX_X2:
-                if (vk == 0) return pick3<S, AX_X2, 2, 0>(n, t);
+                if (vk == 0) return pick3<S, AX_X2, 2, 0, NT>(n, t);
                 break;
             case AX_Y1:
-                if (vk == 1) return pick3<S, AX_Y1, 2, 1>(n, t);
-                if (vk == 2) return pick3<S, AX_Y1, 2, 2>(n, t);
+                if (vk == 1) return pick3<S, AX_Y1, 2, 1, NT>(n, t);
+                if (vk == 2) return pick3<S, AX_Y1, 2, 2, NT>(n, t);
                 break;
             case AX_Y2:
-                if (vk == 1) return pick3<S, AX_Y2, 2, 1>(n, t);
-                if (vk == 2) return pick3<S, AX_Y2, 2, 2>(n, t);
+                if (vk == 1) return pick3<S, AX_Y2, 2, 1, NT>(n, t);
+                if (vk == 2) return pick3<S, AX_Y2, 2, 2, NT>(n, t);
                 break;
             default: break;
         }
@@ -323,26 +323,31 @@ AxisKernel pick_axis3(int axis, int n, int vk, int nst, int* t) {
     }
     switch (axis) {
         case AX_X1:
-            if (vk == 0) return pick3<S, AX_X1, 1, 0>(n, t);
+            if (vk == 0) return pick3<S, AX_X1, 1, 0, NT>(n, t);
             break;
         case AX_X2:
-            if (vk == 0) return pick3<S, AX_X2, 1, 0>(n, t);
-            if (vk == 1) return pick3<S, AX_X2, 1, 1>(n, t);
-            if (vk == 2) return pick3<S, AX_X2, 1, 2>(n, t);
+            if (vk == 0) return pick3<S, AX_X2, 1, 0, NT>(n, t);
+            if (vk == 1) return pick3<S, AX_X2, 1, 1, NT>(n, t);
+            if (vk == 2) return pick3<S, AX_X2, 1, 2, NT>(n, t);
             break;
         case AX_Y1:
-            if (vk == 0) return pick3<S, AX_Y1, 1, 0>(n, t);
-            if (vk == 1) return pick3<S, AX_Y1, 1, 1>(n, t);
-            if (vk == 2) return pick3<S, AX_Y1, 1, 2>(n, t);
+            if (vk == 0) return pick3<S, AX_Y1, 1, 0, NT>(n, t);
+            if (vk == 1) return pick3<S, AX_Y1, 1, 1, NT>(n, t);
+            if (vk == 2) return pick3<S, AX_Y1, 1, 2, NT>(n, t);
             break;
         case AX_Y2:
-            if (vk == 1) return pick3<S, AX_Y2, 1, 1>(n, t);
-            if (vk == 2) return pick3<S, AX_Y2, 1, 2>(n, t);
+            if (vk == 1) return pick3<S, AX_Y2, 1, 1, NT>(n, t);
+            if (vk == 2) return pick3<S, AX_Y2, 1, 2, NT>(n, t);
             break;
         default: break;
     }
     *t = 0;
     return nullptr;
+}
+
+template <class S>
+AxisKernel pick_axis3(int axis, int n, int vk, int nst, bool nt, int* t) {
+    return nt ? pick_axis3_nt<S, true>(axis, n, vk, nst, t) : pick_axis3_nt<S, false>(axis, n, vk, nst, t);
 }
 
 }  // namespace dev

@@ -2,7 +2,7 @@
 #include "axis_pass.hpp"
 
 namespace hom4d_impl {
-dev::AxisKernel pick_axis_f32_2(int axis, int n, int vk, int* t) {
-    return dev::pick_axis<float2, 2>(axis, n, vk, t);
+dev::AxisKernel pick_axis_f32_2(int axis, int n, int vk, bool nt, int* t) {
+    return dev::pick_axis<float2, 2>(axis, n, vk, nt, t);
 }
 }  // namespace hom4d_impl

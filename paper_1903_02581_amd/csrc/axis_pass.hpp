@@ -13,26 +13,55 @@ namespace hom4d_impl {
 namespace dev {
 using namespace hom4d_dev;
 
-template <class S>
-__device__ __forceinline__ double2 ld(const S* p);
-template <>
-__device__ __forceinline__ double2 ld<double2>(const double2* p) {
-    return *p;
+// State loads and stores, widened to / narrowed from FP64.  NT marks them
+// non-temporal (the nt bit of the global load/store): the passes over states
+// several times the 256 MB Infinity Cache stream every element once, and
+// keeping them out of the caches leaves room for the factor tables; smaller
+// states keep the default policy, which lets one pass hit what the previous
+// one wrote.
+typedef double ntv_d2 __attribute__((ext_vector_type(2)));
+typedef float ntv_f2 __attribute__((ext_vector_type(2)));
+template <class S, bool NT = false>
+__device__ __forceinline__ double2 ld(const S* p) {
+    if constexpr (std::is_same<S, double2>::value) {
+        if constexpr (NT) {
+            const ntv_d2 r = __builtin_nontemporal_load(reinterpret_cast<const ntv_d2*>(p));
+            return make_double2(r.x, r.y);
+        } else {
+            return *p;
+        }
+    } else {
+        static_assert(std::is_same<S, float2>::value, "complex128 or complex64 storage");
+        if constexpr (NT) {
+            const ntv_f2 f = __builtin_nontemporal_load(reinterpret_cast<const ntv_f2*>(p));
+            return make_double2((double)f.x, (double)f.y);
+        } else {
+            const float2 f = *p;
+            return make_double2((double)f.x, (double)f.y);
+        }
+    }
 }
-template <>
-__device__ __forceinline__ double2 ld<float2>(const float2* p) {
-    const float2 f = *p;
-    return make_double2((double)f.x, (double)f.y);
-}
-template <class S>
-__device__ __forceinline__ void st(S* p, double2 v);
-template <>
-__device__ __forceinline__ void st<double2>(double2* p, double2 v) {
-    *p = v;
-}
-template <>
-__device__ __forceinline__ void st<float2>(float2* p, double2 v) {
-    *p = make_float2((float)v.x, (float)v.y);
+template <class S, bool NT = false>
+__device__ __forceinline__ void st(S* p, double2 v) {
+    if constexpr (std::is_same<S, double2>::value) {
+        if constexpr (NT) {
+            ntv_d2 r;
+            r.x = v.x;
+            r.y = v.y;
+            __builtin_nontemporal_store(r, reinterpret_cast<ntv_d2*>(p));
+        } else {
+            *p = v;
+        }
+    } else {
+        if constexpr (NT) {
+            ntv_f2 r;
+            r.x = (float)v.x;
+            r.y = (float)v.y;
+            __builtin_nontemporal_store(r, reinterpret_cast<ntv_f2*>(p));
+        } else {
+            *p = make_float2((float)v.x, (float)v.y);
+        }
+    }
 }
 
 // Element type of an LDS exchange of the state: complex64 with complex64
@@ -186,7 +215,7 @@ struct LineGeom {
 };
 
 // VK: 0 = no potential factor on this pass, 1 = table form, 2 = per-point form.
-template <class S, int AXIS, int N1, int N2, int T, int NST, int VK>
+template <class S, int AXIS, int N1, int N2, int T, int NST, int VK, bool NT>
 __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     constexpr int N = N1 * N2;
     constexpr int E = N / T;
@@ -267,7 +296,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         for (int n1 = 0; n1 < N1; ++n1) {
             const int64_t off = (int64_t)(n1 * N2 + jc) * sN;
 #pragma unroll
-            for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = ld<S>(ps[s] + off);
+            for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = ld<S, NT>(ps[s] + off);
         }
     }
 
@@ -428,7 +457,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         for (int n1 = 0; n1 < N1; ++n1) {
             const int64_t off = (int64_t)(n1 * N2 + jc) * sN;
 #pragma unroll
-            for (int s = 0; s < NST; ++s) st<S>(ps[s] + off, v[s][jj * N1 + n1]);
+            for (int s = 0; s < NST; ++s) st<S, NT>(ps[s] + off, v[s][jj * N1 + n1]);
         }
     }
 
@@ -495,21 +524,19 @@ struct LineTables {
 
 using AxisKernel = void (*)(const PassArgs);
 
-template <class S, int AXIS, int NST, int VK>
+// Line lengths of the two-stage kernel (96, 128 and 256 take the three-stage one).
+template <class S, int AXIS, int NST, int VK, bool NT>
 AxisKernel pick(int n, int* t) {
     switch (n) {
-        case 4: *t = 1; return k_axis<S, AXIS, 4, 1, 1, NST, VK>;
-        case 6: *t = 1; return k_axis<S, AXIS, 6, 1, 1, NST, VK>;
-        case 8: *t = 1; return k_axis<S, AXIS, 8, 1, 1, NST, VK>;
-        case 12: *t = 1; return k_axis<S, AXIS, 12, 1, 1, NST, VK>;
-        case 16: *t = 4; return k_axis<S, AXIS, 4, 4, 4, NST, VK>;
-        case 24: *t = 2; return k_axis<S, AXIS, 12, 2, 2, NST, VK>;
-        case 32: *t = 4; return k_axis<S, AXIS, 8, 4, 4, NST, VK>;
-        case 48: *t = 4; return k_axis<S, AXIS, 12, 4, 4, NST, VK>;
-        case 64: *t = 8; return k_axis<S, AXIS, 8, 8, 8, NST, VK>;
-        case 96: *t = 4; return k_axis<S, AXIS, 12, 8, 4, NST, VK>;
-        case 128: *t = 8; return k_axis<S, AXIS, 16, 8, 8, NST, VK>;
-        case 256: *t = 16; return k_axis<S, AXIS, 16, 16, 16, NST, VK>;
+        case 4: *t = 1; return k_axis<S, AXIS, 4, 1, 1, NST, VK, NT>;
+        case 6: *t = 1; return k_axis<S, AXIS, 6, 1, 1, NST, VK, NT>;
+        case 8: *t = 1; return k_axis<S, AXIS, 8, 1, 1, NST, VK, NT>;
+        case 12: *t = 1; return k_axis<S, AXIS, 12, 1, 1, NST, VK, NT>;
+        case 16: *t = 4; return k_axis<S, AXIS, 4, 4, 4, NST, VK, NT>;
+        case 24: *t = 2; return k_axis<S, AXIS, 12, 2, 2, NST, VK, NT>;
+        case 32: *t = 4; return k_axis<S, AXIS, 8, 4, 4, NST, VK, NT>;
+        case 48: *t = 4; return k_axis<S, AXIS, 12, 4, 4, NST, VK, NT>;
+        case 64: *t = 8; return k_axis<S, AXIS, 8, 8, 8, NST, VK, NT>;
         default: *t = 0; return nullptr;
     }
 }
@@ -517,30 +544,35 @@ AxisKernel pick(int n, int* t) {
 // Variants built: vk = 0 (no potential factor), 1 (table form), 2 (per-point
 // form).  The x1 pass never carries the factor; the reverse (two-state) sweep
 // carries it on the y passes only; the forward plans put it on x2, y1 or y2.
-template <class S, int AXIS, int NST>
+template <class S, int AXIS, int NST, bool NT>
 AxisKernel pick_vk(int n, int vk, int* t) {
     constexpr bool with_v = (NST == 1) ? (AXIS != AX_X1) : (AXIS == AX_Y1 || AXIS == AX_Y2);
     constexpr bool without_v = (AXIS == AX_X1 || AXIS == AX_X2 || (NST == 1 && AXIS == AX_Y1));
     if constexpr (with_v) {
-        if (vk == 1) return pick<S, AXIS, NST, 1>(n, t);
-        if (vk == 2) return pick<S, AXIS, NST, 2>(n, t);
+        if (vk == 1) return pick<S, AXIS, NST, 1, NT>(n, t);
+        if (vk == 2) return pick<S, AXIS, NST, 2, NT>(n, t);
     }
     if constexpr (without_v) {
-        if (vk == 0) return pick<S, AXIS, NST, 0>(n, t);
+        if (vk == 0) return pick<S, AXIS, NST, 0, NT>(n, t);
     }
     *t = 0;
     return nullptr;
 }
 
-template <class S, int NST>
-AxisKernel pick_axis(int axis, int n, int vk, int* t) {
+template <class S, int NST, bool NT>
+AxisKernel pick_axis_nt(int axis, int n, int vk, int* t) {
     switch (axis) {
-        case AX_X1: return pick_vk<S, AX_X1, NST>(n, vk, t);
-        case AX_X2: return pick_vk<S, AX_X2, NST>(n, vk, t);
-        case AX_Y1: return pick_vk<S, AX_Y1, NST>(n, vk, t);
-        case AX_Y2: return pick_vk<S, AX_Y2, NST>(n, vk, t);
+        case AX_X1: return pick_vk<S, AX_X1, NST, NT>(n, vk, t);
+        case AX_X2: return pick_vk<S, AX_X2, NST, NT>(n, vk, t);
+        case AX_Y1: return pick_vk<S, AX_Y1, NST, NT>(n, vk, t);
+        case AX_Y2: return pick_vk<S, AX_Y2, NST, NT>(n, vk, t);
         default: *t = 0; return nullptr;
     }
+}
+
+template <class S, int NST>
+AxisKernel pick_axis(int axis, int n, int vk, bool nt, int* t) {
+    return nt ? pick_axis_nt<S, NST, true>(axis, n, vk, t) : pick_axis_nt<S, NST, false>(axis, n, vk, t);
 }
 
 }  // namespace dev

@@ -30,6 +30,7 @@ struct PassArgs {
     const double2* tw2;       // plane pass only: twiddles of the y lines
     const double2* ktab2;     // plane pass only: y kinetic factor [ny]
     int vmode;                // 0: none, 1: potential factor before the transform, 2: after
+    int nt;                   // line passes: non-temporal state loads and stores (large states)
     // potential factor, table form
     const double2* a1;        // [nx*ny]  exp(-i tau V(x,y)/hbar)
     const double2* ac;        // [(2nx-1)*(2ny-1)] exp(-i tau V12(dx,dy)/hbar), or null

@@ -31,12 +31,12 @@ using namespace hom4d_dev;
 namespace hom4d_impl {
 
 using dev::AxisKernel;
-AxisKernel pick_axis_f64_1(int axis, int n, int vk, int* t);
-AxisKernel pick_axis_f64_2(int axis, int n, int vk, int* t);
-AxisKernel pick_axis_f32_1(int axis, int n, int vk, int* t);
-AxisKernel pick_axis_f32_2(int axis, int n, int vk, int* t);
-AxisKernel pick_axis3_f64(int axis, int n, int vk, int nst, int* t);
-AxisKernel pick_axis3_f32(int axis, int n, int vk, int nst, int* t);
+AxisKernel pick_axis_f64_1(int axis, int n, int vk, bool nt, int* t);
+AxisKernel pick_axis_f64_2(int axis, int n, int vk, bool nt, int* t);
+AxisKernel pick_axis_f32_1(int axis, int n, int vk, bool nt, int* t);
+AxisKernel pick_axis_f32_2(int axis, int n, int vk, bool nt, int* t);
+AxisKernel pick_axis3_f64(int axis, int n, int vk, int nst, bool nt, int* t);
+AxisKernel pick_axis3_f32(int axis, int n, int vk, int nst, bool nt, int* t);
 AxisKernel pick_plane_f64(int nx, int ny, int vk, int* nt);
 AxisKernel pick_plane_f32(int nx, int ny, int vk, int* nt);
 
@@ -240,12 +240,13 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
     int t = 0;
     AxisKernel fn = nullptr;
     const int vk = a.vmode == 0 ? 0 : (a.vdirect ? 2 : 1);
+    const bool nt = a.nt != 0;
     if (axis3_threads(n, nst) > 0)
-        fn = mixed ? pick_axis3_f32(axis, n, vk, nst, &t) : pick_axis3_f64(axis, n, vk, nst, &t);
+        fn = mixed ? pick_axis3_f32(axis, n, vk, nst, nt, &t) : pick_axis3_f64(axis, n, vk, nst, nt, &t);
     else if (!mixed)
-        fn = (nst == 2) ? pick_axis_f64_2(axis, n, vk, &t) : pick_axis_f64_1(axis, n, vk, &t);
+        fn = (nst == 2) ? pick_axis_f64_2(axis, n, vk, nt, &t) : pick_axis_f64_1(axis, n, vk, nt, &t);
     else
-        fn = (nst == 2) ? pick_axis_f32_2(axis, n, vk, &t) : pick_axis_f32_1(axis, n, vk, &t);
+        fn = (nst == 2) ? pick_axis_f32_2(axis, n, vk, nt, &t) : pick_axis_f32_1(axis, n, vk, nt, &t);
     if (!fn || a.W <= 0 || nlines % a.W != 0) return hipErrorInvalidValue;
     const int64_t nblocks = nlines / a.W;
     const int max_threads = axis3_threads(n, nst) > 0 ? axis3_block_threads(axis, n, nst, mixed) : 256;
