@@ -403,14 +403,16 @@ int run_pass(hom4d* h, int axis, KTab kt, int vmode, int nst, void* lam, bool re
     else
         a.ktab = kt == KX_HALF ? h->kx_half : (kt == KX_FULL ? h->kx_full : h->ky_full);
     a.vmode = vmode;
-    // Non-temporal state accesses for states over 1 GiB (four times the 256 MB
-    // Infinity Cache), where each pass streams the state through once: 256x128
-    // complex64 23.55 -> 22.01 ms per step, 128x128 FP64 7.18 -> 6.77, 128x96
-    // FP64 3.90 -> 3.70, 128x96 complex64 2.715 -> 2.667.  Below that the
-    // default policy wins (64x64 FP64 288 -> 332 us with them, 128x64
-    // complex64 1.093 -> 1.118 ms), since one pass then hits what the
-    // previous one wrote.
-    a.nt = h->state_bytes > (size_t(1) << 30) ? 1 : 0;
+    // Non-temporal state accesses where each pass streams the state through
+    // once: on every pass for states over 1 GiB (four times the 256 MB
+    // Infinity Cache; 256x128 complex64 23.55 -> 22.01 ms per step, 128x128
+    // FP64 7.18 -> 6.77, 128x96 FP64 3.90 -> 3.70, 128x96 complex64 2.715 ->
+    // 2.667), and on the x1 pass from 512 MiB (128x64 FP64 1.572 -> 1.524 ms,
+    // complex64 1.096 -> 1.083; all passes there were slower, and x1 with x2
+    // let the following y1 pass lose its cache hits).  Smaller states keep
+    // the default policy (64x64 FP64 288 -> 332 us with it), since one pass
+    // then hits what the previous one wrote.
+    a.nt = (h->state_bytes > (size_t(1) << 30) || (axis == AX_X1 && h->state_bytes >= (size_t(1) << 29))) ? 1 : 0;
     a.a1 = h->a1_half;
     a.ac = (c.coulomb_c != 0.0) ? h->ac_half : nullptr;
     a.vdirect = c.coulomb_mode == HOM4D_COULOMB_DIRECT ? 1 : 0;
