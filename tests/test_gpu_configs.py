@@ -182,6 +182,52 @@ def test_full_scale_short_run():
         torch.cuda.empty_cache()
 
 
+def test_large_state_short_y_axis():
+    """256x64 per electron (2.7e8 points; FP64 state 4.3 GB, complex64 2.1 GB): past 1 GiB every
+    pass takes non-temporal state accesses, including the two-stage kernel of the n = 64 y lines.
+    Both precisions against the 2D oracle through the V12 = 0 factorisation, then a short
+    adjoint (dual-state passes with the same cache policy): FP64 against complex64 and the gauge
+    identity sum dL/dV = 0."""
+    import torch
+    from workloads.presets import build
+    from paper_1903_02581_amd import Propagator
+    w = build("wide", 256, 64, 2000.0, 500.0, b_tesla=5.0, dt_fs=0.5, steps=12, sigma_x=20.0,
+              coulomb_c=0.0, seed=7)
+    announce(f"256x64 ({w.points} points) V12=0 steps={w.steps} both precisions + adjoint")
+    a, b, scale = _factorised_reference(w, w.steps)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-4)):
+        p = Propagator.from_workload(w, precision=prec)
+        assert p.passes_per_step == 4
+        p.step(w.steps)
+        o = p.observables(w.w_top)
+        flat = p.psi
+
+        def get(idx):
+            return flat[torch.as_tensor(idx, device=flat.device)].cpu().numpy().astype(np.complex128)
+
+        p_tt = _check_factorised(get, w, a, b, scale, tol, seed=3)
+        assert abs(o["p_tt"] - p_tt) <= tol
+        p.close()
+        del p, flat
+        torch.cuda.empty_cache()
+    res = {}
+    for prec in ("fp64", "mixed"):
+        p = Propagator.from_workload(w, precision=prec)
+        p.set_norm_tol(1.0)
+        p.grad_begin(4, 8)
+        p.step(8)
+        res[prec] = p.grad_backward(w.w_top)
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+    (l64, v64, b64), (l32, v32, b32) = res["fp64"], res["mixed"]
+    assert np.all(np.isfinite(v64)) and np.isfinite(b64)
+    assert abs(v64.sum()) <= 1e-10 * np.abs(v64).sum()
+    assert abs(l32 - l64) <= 1e-6 * max(abs(l64), 1e-12) + 1e-12
+    assert np.max(np.abs(v32 - v64)) <= 1e-4 * np.max(np.abs(v64))
+    assert abs(b32 - b64) <= 1e-4 * abs(b64) + 1e-12
+
+
 def test_maximum_size_256x256():
     """The largest supported grid, 256x256 per electron: 4.3e9 points, past 32-bit point
     indices (a complex128 state of 68.7 GB, complex64 34.4 GB).  Both precisions against the
