@@ -115,13 +115,19 @@ size_t hom4d_state_bytes(const hom4d_cfg* cfg);
  * aligned).  Rebinding discards any gradient recording. */
 int hom4d_bind_state(hom4d* h, void* d_psi);
 
-/* External potential V(x, y) in meV, host row-major [nx][ny] FP64, the same
- * for both electrons.  Rebuilds the potential phase tables and discards any
- * gradient recording (its forward run used the old factors). */
+/* External potential V(x, y) in meV, host row-major [nx][ny] FP64: the
+ * one-body terms V(r1) + V(r2) of the two-particle Hamiltonian of Appendix A
+ * (the same confinement and beam-splitter potential for both electrons,
+ * Sec. II.B, Eq. (pot_x) / Eq. (pot_xy)), entering the real-space factor of
+ * Eq. (evoloperat).  Rebuilds the potential phase tables and discards any
+ * gradient recording (its forward run used the old factors).  EINVAL on a
+ * NULL pointer or a non-finite entry. */
 int hom4d_set_potential(hom4d* h, const double* v_meV);
 
-/* Change B (tesla); rebuilds the x kinetic phase tables and discards any
- * gradient recording. */
+/* Change B (tesla), the perpendicular field of Sec. II.A and Appendix A.  In
+ * the Landau gauge A = (-B y, 0) it enters only the x kinetic term
+ * (hbar k_x - e B y)^2 / 2m*, so this rebuilds the x kinetic phase tables and
+ * discards any gradient recording.  EINVAL on a non-finite B. */
 int hom4d_set_field(hom4d* h, double b_tesla);
 
 /* Initial state of Sec. II.C Eq. (twopstate) from two single-electron
@@ -172,8 +178,17 @@ size_t hom4d_checkpoint_bytes(const hom4d* h);
 int hom4d_save_checkpoint(hom4d* h, void* buf, size_t bytes);
 int hom4d_load_checkpoint(hom4d* h, const void* buf, size_t bytes);
 
-/* Advance the bound state by n >= 0 whole steps S(dt); asynchronous on the
- * stream.  While a gradient recording is open, also stores the checkpoints. */
+/* Advance the bound state by n >= 0 whole steps of the split-step Fourier
+ * propagator of Sec. II.C, Eq. (evoloperat) and Appendix A: each step is
+ * S(dt) = X(dt/2) V(dt/2) Y(dt) V(dt/2) X(dt/2), with X and Y the kinetic
+ * factors of the two electrons (diagonal in (k_x, y) and k_y) and V the
+ * one-body potentials plus the two-body term of Eq. (coulomb) /
+ * Eq. (screenedCoulomb), diagonal in 4D real space.  Asynchronous on the
+ * stream.  EUNBOUND without a state, ESTATE without a potential.  While a
+ * gradient recording is open it also stores the checkpoints; a call whose
+ * checkpoints would not fit the pool returns ENOMEM before taking any step
+ * (state, step count and recording unchanged), and a failure part way closes
+ * the recording. */
 int hom4d_step(hom4d* h, int64_t n);
 
 /* Region-resolved probabilities of the bound state for the top-region weight
@@ -206,11 +221,14 @@ int hom4d_conditional(hom4d* h, int32_t ix2, int32_t jy2, double* out);
 int hom4d_gather_slice(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1,
                        const int32_t* ix2, int32_t n2, int32_t jy2, double* out);
 
-/* Start recording a forward run for the adjoint.  The current bound state is
- * checkpoint 0; every ckpt_every steps taken by later hom4d_step calls the
- * state is copied into the caller-owned device pool (pool_bytes bytes, slots
- * of hom4d_state_bytes).  hom4d_step returns ENOMEM when the next checkpoint
- * would not fit. */
+/* Start recording a forward run for the adjoint (the reverse-mode derivative
+ * of the bunching probability of Eq. (p_bunching) through the unitary steps of
+ * Eq. (evoloperat); not an operation of the paper itself).  The current bound
+ * state is checkpoint 0; every ckpt_every steps taken by later hom4d_step calls
+ * the state is copied into the caller-owned device pool (pool_bytes bytes,
+ * slots of hom4d_state_bytes).  hom4d_step returns ENOMEM, without stepping,
+ * when a checkpoint it would reach does not fit.  EINVAL on ckpt_every < 1 or
+ * a NULL pool, ENOMEM if the pool is smaller than one state. */
 int hom4d_grad_begin(hom4d* h, int32_t ckpt_every, void* d_pool, size_t pool_bytes);
 
 /* Reverse sweep for L = sum w_L |Psi_N|^2 with
@@ -221,7 +239,8 @@ int hom4d_grad_begin(hom4d* h, int32_t ckpt_every, void* d_pool, size_t pool_byt
  * is replaced by the stored copy (bounds the reverse drift).  Outputs:
  * *loss = L, dL_dV (host [nx][ny] FP64, derivative with respect to the
  * potential table in 1/meV), *dL_dB (1/T).  On return the bound state holds
- * checkpoint 0 and the recording is closed.  ESTATE without a recording. */
+ * checkpoint 0 and the recording is closed.  ESTATE without a recording or
+ * when the recorded checkpoints exceed the pool. */
 int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs,
                         void* d_lambda, double* loss, double* dL_dV, double* dL_dB);
 

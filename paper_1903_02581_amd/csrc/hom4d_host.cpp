@@ -951,22 +951,35 @@ int hom4d_step(hom4d* h, int64_t n) {
         h->step += n;
         return HOM4D_OK;
     }
-    // recording: close the state on every checkpoint boundary and copy it out
+    // recording: every checkpoint these n steps reach must fit the pool, checked
+    // before anything runs, so that a refused call leaves the state, the step
+    // count and the recording as they were
+    const int64_t last_slot = (h->rec_steps + n) / h->ckpt_every;
+    if ((size_t)(last_slot + 1) * h->state_bytes > h->pool_bytes)
+        return fail(HOM4D_ENOMEM, "checkpoint %lld does not fit the pool (%zu bytes)", (long long)last_slot,
+                    h->pool_bytes);
+    // close the state on every checkpoint boundary and copy it out; a failure
+    // part way closes the recording (its checkpoints no longer match the state)
     int64_t left = n;
     while (left > 0) {
         const int64_t to_ck = h->ckpt_every - (h->rec_steps % h->ckpt_every);
         const int64_t m = std::min(left, to_ck);
         int rc = run_steps(h, m, 1, nullptr, false, nullptr);
-        if (rc) return rc;
+        if (rc) {
+            h->rec = false;
+            return rc;
+        }
         h->rec_steps += m;
         h->step += m;
         left -= m;
         if (h->rec_steps % h->ckpt_every == 0) {
             const size_t slot = (size_t)(h->rec_steps / h->ckpt_every);
-            if ((slot + 1) * h->state_bytes > h->pool_bytes)
-                return fail(HOM4D_ENOMEM, "checkpoint %zu does not fit the pool (%zu bytes)", slot, h->pool_bytes);
-            HIP_TRY(hipMemcpyAsync(h->pool + slot * h->state_bytes, h->psi, h->state_bytes, hipMemcpyDeviceToDevice,
-                                   h->stream));
+            const hipError_t e = hipMemcpyAsync(h->pool + slot * h->state_bytes, h->psi, h->state_bytes,
+                                                hipMemcpyDeviceToDevice, h->stream);
+            if (e != hipSuccess) {
+                h->rec = false;
+                return fail(HOM4D_EHIP, "checkpoint copy: %s", hipGetErrorString(e));
+            }
         }
     }
     return HOM4D_OK;
@@ -1114,6 +1127,8 @@ int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs, voi
     if (rc) return rc;
     if (!h->rec) return fail(HOM4D_ESTATE, "no recorded forward run (hom4d_grad_begin + hom4d_step)");
     if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    if ((size_t)(h->rec_steps / h->ckpt_every + 1) * h->state_bytes > h->pool_bytes)
+        return fail(HOM4D_ESTATE, "recorded checkpoints exceed the pool (%zu bytes)", h->pool_bytes);
     const hom4d_cfg& c = h->cfg;
     const AxisPlan px1 = plan_axis(AX_X1, c.nx, c.ny, 2, true, h->mixed);
     const AxisPlan px2 = plan_axis(AX_X2, c.nx, c.ny, 2, true, h->mixed);

@@ -135,6 +135,47 @@ def test_mixed_config_error_budget():
     assert abs(o64["norm"] - 1.0) <= 1e-10
 
 
+@pytest.mark.parametrize("mode", ["table", "direct"])
+def test_mixed_config_coulomb_vs_oracle(mode):
+    """128x96 per electron with the softened Coulomb term on (d = 1 nm), two steps in the
+    launch configuration the benchmark times (four passes, three-stage kernels at n = 96 and
+    128, non-temporal state accesses past 1 GiB), both storages, against the FP64 oracle:
+    relative L2 of the whole state and the region probabilities."""
+    import torch
+    from paper_1903_02581_amd import Propagator
+    w = preset("mixed")
+    steps = 2
+    announce(f"mixed config 128x96 Coulomb on ({mode}) steps={steps} vs oracle, both storages")
+    ref, _ = _mixed_oracle_two_steps(w, steps)
+    ro = O.observables(ref, w.w_top)
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-4)):
+        p = Propagator.from_workload(w, precision=prec, coulomb_mode=mode)
+        assert p.passes_per_step == 4
+        p.step(steps)
+        o = p.observables(w.w_top)
+        psi = p.store_state()
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+        err = rel_l2(psi, ref)
+        announce(f"128x96 Coulomb {mode} {prec}: rel L2 {err:.3e}, |dP_b| {abs(o['p_b'] - ro['p_b']):.3e}")
+        assert err <= tol
+        for k in ("p_tt", "p_tb", "p_bt", "p_bb", "norm"):
+            assert abs(o[k] - ro[k]) <= (1e-12 if prec == "fp64" else 1e-5), k
+        del psi
+
+
+_ORACLE_CACHE = {}
+
+
+def _mixed_oracle_two_steps(w, steps):
+    key = (w.name, steps)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE.clear()
+        _ORACLE_CACHE[key] = oracle_run(w, steps)
+    return _ORACLE_CACHE[key]
+
+
 def test_mixed_config_factorisation_without_coulomb():
     from paper_1903_02581_amd import Propagator
     w = preset("mixed", coulomb_c=0.0)
@@ -308,7 +349,7 @@ def test_diff_config_gradient_vs_finite_differences():
     announce(f"diff grads fp64={g64} fd={fd} mixed={g32}")
     scale = np.max(np.abs(g64))
     assert np.max(np.abs(g64 - fd)) <= 1e-5 * scale
-    assert np.max(np.abs(g32 - g64)) <= 1e-3 * scale
+    assert np.max(np.abs(g32 - g64)) <= 1e-4 * scale
 
 
 def test_full_scale_adjoint():

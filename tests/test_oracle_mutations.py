@@ -115,9 +115,24 @@ def _dtheta_db_sign(g, tau):
     return -_ORIG["dtheta_x_db"](g, tau)
 
 
+def _loss_bb_term_transposed(w_top, coeffs=(1.0, 0.0, 0.0, 1.0)):
+    # the (B, B) term weighted by (1 - w1) w2 instead of (1 - w1)(1 - w2)
+    w = np.asarray(w_top, dtype=np.float64)
+    w1, w2 = w[:, :, None, None], w[None, None, :, :]
+    a_tt, a_tb, a_bt, a_bb = coeffs
+    return (a_tt * w1 * w2 + a_tb * w1 * (1 - w2) + a_bt * (1 - w1) * w2
+            + a_bb * (1 - w1) * w2)
+
+
+def _loss_tb_bt_swapped(w_top, coeffs=(1.0, 0.0, 0.0, 1.0)):
+    a_tt, a_tb, a_bt, a_bb = coeffs
+    return _ORIG["loss_weights"](w_top, (a_tt, a_bt, a_tb, a_bb))
+
+
 # unmutated functions, for the mutations that wrap them
 _ORIG = {"observables": OB.observables, "init_state": SS.init_state,
-         "entanglement": OB.entanglement, "coulomb": SS.coulomb, "dtheta_x_db": SS.dtheta_x_db}
+         "entanglement": OB.entanglement, "coulomb": SS.coulomb, "dtheta_x_db": SS.dtheta_x_db,
+         "loss_weights": AD.loss_weights}
 
 
 MUTATIONS = {
@@ -134,6 +149,8 @@ MUTATIONS = {
     "symmetric state for sym = -1": ("init_state", _init_always_symmetric, ["p3"]),
     "entropy in bits": ("entanglement", _entropy_in_bits, ["p8"]),
     "d theta_X / dB with the wrong sign": ("dtheta_x_db", _dtheta_db_sign, ["p7"]),
+    "loss weight of (B, B) taken as (1 - w1) w2": ("loss_weights", _loss_bb_term_transposed, ["loss"]),
+    "loss coefficients of TB and BT swapped": ("loss_weights", _loss_tb_bt_swapped, ["loss"]),
 }
 
 
@@ -154,6 +171,8 @@ def _run_pin(name):
         return _fails(pins.test_p8_entanglement_special_cases)
     if name == "obs":
         return _fails(pins.test_orbital_observables_brute_force, 0)
+    if name == "loss":
+        return _fails(pins.test_loss_weights_are_region_probabilities)
     raise KeyError(name)
 
 
@@ -169,5 +188,5 @@ def test_pins_catch_planted_mistake(label, monkeypatch):
 
 
 def test_pins_pass_unmutated():
-    for name in ("p2", "p4", "p3", "p8", "obs"):
+    for name in ("p2", "p4", "p3", "p8", "obs", "loss"):
         assert not _run_pin(name), name

@@ -302,6 +302,64 @@ def test_p7_adjoint_vs_finite_differences():
         assert abs(fd_ij - g_v[i, j]) <= 1e-6 * max(abs(fd_ij), 1e-8)
 
 
+def _region_probabilities_by_loops(psi, top):
+    """P_TT, P_TB, P_BT, P_BB of Eq. (p_bunching), Sec. III, for a hard partition of the
+    one-electron plane: top[i, j] is True where (x_i, y_j) lies in T.  Each grid point of
+    configuration space is visited once and its |Psi|^2 goes to the one region pair its
+    two electrons occupy (pure-Python loops, no weight algebra)."""
+    nx, ny = top.shape
+    acc = {"TT": 0.0, "TB": 0.0, "BT": 0.0, "BB": 0.0}
+    for i1 in range(nx):
+        for j1 in range(ny):
+            for i2 in range(nx):
+                for j2 in range(ny):
+                    key = ("T" if top[i1, j1] else "B") + ("T" if top[i2, j2] else "B")
+                    z = psi[i1, j1, i2, j2]
+                    acc[key] += z.real * z.real + z.imag * z.imag
+    return acc
+
+
+def test_loss_weights_are_region_probabilities():
+    """The loss of the adjoint is the bunching probability of Eq. (p_bunching), Sec. III:
+    with coefficients (1, 0, 0, 1) it is the probability that both electrons sit in the
+    same region, and with a unit coefficient vector it is that region pair's probability.
+    Checked for a hard T/B partition against sums by explicit loops over configuration
+    space, on the initial state (zero steps) and after two Strang steps, where it must also
+    equal the bunching probability of observables() of the propagated state."""
+    from workloads.presets import build
+    nx, ny = 4, 6
+    w = build("g", nx, ny, 100.0, 150.0, b_tesla=5.0, dt_fs=5.0, steps=2, sigma_x=20.0, seed=4,
+              sym=0)
+    g = O.make_grid(nx, ny, w.lx, w.ly, b_tesla=w.b_tesla, soft_nm=w.soft_nm, coulomb_c=1.0)
+    rng = np.random.default_rng(17)
+    top = rng.uniform(size=(nx, ny)) < 0.5        # an irregular partition, both regions used
+    top[0, 0], top[0, 1] = True, False
+    w_top = top.astype(np.float64)
+    psi0 = O.init_state(w.psi_a, w.psi_b, 0)      # product state: P_TB != P_BT
+    units = {"TT": (1, 0, 0, 0), "TB": (0, 1, 0, 0), "BT": (0, 0, 1, 0), "BB": (0, 0, 0, 1)}
+    for steps in (0, 2):
+        psi = O.propagate(psi0, g, w.v_table, w.dt_fs, steps) if steps else psi0
+        ref = _region_probabilities_by_loops(psi, top)
+        assert abs(ref["TB"] - ref["BT"]) > 1e-6  # the pairs are distinguishable here
+        for key, cf in units.items():
+            loss, _, _ = O.loss_and_grad_stored(psi0, g, w.v_table, w.dt_fs, steps, w_top,
+                                                coeffs=cf)
+            assert abs(loss - ref[key]) < 1e-14, (steps, key, loss, ref[key])
+        loss, _, _ = O.loss_and_grad_stored(psi0, g, w.v_table, w.dt_fs, steps, w_top)
+        assert abs(loss - (ref["TT"] + ref["BB"])) < 1e-14
+        assert abs(loss - O.observables(psi, w_top)["p_b"]) < 1e-14
+    # soft weights (w in [0, 1]): the four region-pair losses partition the norm, and the
+    # loss is linear in the coefficients
+    w_soft = rng.uniform(size=(nx, ny))
+    parts = [O.loss_and_grad_stored(psi0, g, w.v_table, w.dt_fs, 0, w_soft, coeffs=cf)[0]
+             for cf in units.values()]
+    norm = float(np.sum(np.abs(psi0) ** 2))
+    assert abs(sum(parts) - norm) < 1e-14
+    cf = (0.3, -1.2, 2.5, 0.7)
+    mix = O.loss_and_grad_stored(psi0, g, w.v_table, w.dt_fs, 0, w_soft, coeffs=cf)[0]
+    assert abs(mix - sum(c * q for c, q in zip(cf, parts))) < 1e-13
+
+
 # --------------------------------------------------------------- P8: entanglement
 
 def test_p8_entanglement_special_cases():
