@@ -19,6 +19,19 @@
 // stages the line is exchanged through LDS, each stage reading and writing its
 // own disjoint set of positions.
 //
+// PERS (forward one-state passes only): the kernel is persistent: a block
+// walks tiles of W lines (tile = blockIdx.x, + gridDim.x, ...) and issues the
+// loads of its next tile before it transforms the current one, so that the HBM
+// reads of one tile overlap the arithmetic and LDS exchanges of the previous
+// one inside the block, instead of relying on other resident blocks being out
+// of phase.  Its exchanges synchronise the block on LDS alone (lds_barrier),
+// leaving the prefetch loads and the stores in flight.  It pays where a pass
+// has few resident blocks per CU: measured on the complex64 x1 and y1 passes
+// of the 256x128 state (x1 6.07 -> 5.36 ms, y1 4.46 -> 4.20 ms); the x2 and
+// y2 passes, the FP64 passes and n = 96 lines ran slower that way (128x96
+// complex64 y1 0.52 -> 0.61 ms, y2 0.72 -> 0.86 ms; 128x128 FP64 x1 1.62 ->
+// 1.79 ms), so they keep one tile per block.
+//
 // The arithmetic is FP64 for both storage types.  With complex64 storage the
 // exchange area holds complex64 too: each exchange then rounds like one more
 // store of the state (random, not coherent, since the state changes every
@@ -41,8 +54,41 @@ struct Net3 {
     static_assert(G1 * R2 == E && G2 * R3 == E, "every stage must give a thread E elements");
 };
 
-template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT>
+// Block-wide synchronisation on LDS only: wait for this wave's LDS accesses,
+// then the barrier.  Global loads and stores stay in flight (a fence-carrying
+// __syncthreads would wait for them); the memory clobber keeps the compiler
+// from moving LDS accesses across it.  Exchanges along y2 with T | 64 stay
+// wave-local as in line_sync.
+template <int AXIS, int T>
+__device__ __forceinline__ void lds_barrier() {
+    if constexpr (AXIS == AX_Y2 && 64 % T == 0)
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    else
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// State element as stored (complex128 or complex64), no widening: the
+// prefetch registers of the persistent passes hold the next tile this way.
+template <class S, bool NT>
+__device__ __forceinline__ S ld_raw(const S* p) {
+    if constexpr (NT) {
+        if constexpr (std::is_same<S, double2>::value) {
+            const ntv_d2 r = __builtin_nontemporal_load(reinterpret_cast<const ntv_d2*>(p));
+            return make_double2(r.x, r.y);
+        } else {
+            const ntv_f2 r = __builtin_nontemporal_load(reinterpret_cast<const ntv_f2*>(p));
+            return make_float2(r.x, r.y);
+        }
+    } else {
+        return *p;
+    }
+}
+__device__ __forceinline__ double2 widen(double2 v) { return v; }
+__device__ __forceinline__ double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
+template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT, bool PERS>
 __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !std::is_same<S, double2>::value)) k_axis3(const PassArgs a) {
+    static_assert(!PERS || NST == 1, "only the forward passes are persistent");
     using NW = Net3<R1, R2, R3, T>;
     constexpr int N = NW::N, N2 = NW::N2, JA = NW::JA, G1 = NW::G1, G2 = NW::G2, E = NW::E;
     using X = Xchg<S>;
@@ -58,8 +104,6 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         cl = tid % W;
         t = tid / W;
     }
-    const uint32_t line = blockIdx.x * (uint32_t)W + (uint32_t)cl;
-    const LineGeom<AXIS> lg(a, line);
 
     // twiddles w_n^j (and, on y axes, the kinetic factor) staged after the exchange area
     constexpr bool KT_LDS = (AXIS == AX_Y1 || AXIS == AX_Y2);
@@ -81,216 +125,271 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
     // state s, line position pos: s * N + pos rows of W + 1 slots
     auto Lw = [&](int st_, int pos, double2 v) { lds[(st_ * N + pos) * LS + cl] = X::put(v); };
     auto Lr = [&](int st_, int pos) -> double2 { return X::get(lds[(st_ * N + pos) * LS + cl]); };
+    // the exchanges: LDS-only barriers in the persistent passes
+    auto sync = [&]() {
+        if constexpr (PERS)
+            lds_barrier<AXIS, T>();
+        else
+            line_sync<AXIS, T>();
+    };
+    // element jj * R1 + n1 of a thread: line position n1 N2 + t + T jj
+    auto elem_off = [&](const LineGeom<AXIS>& lg, int jj, int n1) -> int64_t {
+        return (int64_t)(n1 * N2 + t + T * jj) * lg.sN;
+    };
 
-    // the state, and in the reverse sweep the adjoint state beside it
-    S* ps[NST];
-    ps[0] = reinterpret_cast<S*>(a.psi) + lg.base;
-    if constexpr (NST == 2) ps[1] = reinterpret_cast<S*>(a.lam) + lg.base;
+    // Transform round trip of the block's tile held in v (loaded elements in,
+    // the same elements out, stored in place), with the potential factor and
+    // the reverse sweep's gradient terms.
     double2 v[NST][E];
+    auto round_trip = [&](const LineGeom<AXIS>& lg, uint32_t line, S* const* ps) {
+        // gradient accumulators of the reverse sweep: the potential marginal
+        // Im(conj(lambda) psi) on the side of the potential factor the pass is told
+        // to take it (before: G_MIN, after: G_MOUT), and the dL/dB term of the x
+        // kinetic factor in reciprocal space
+        double gm_acc = 0.0, gb_acc = 0.0;
+        if constexpr (NST == 2) {
+            if (a.gflags & G_MIN) {
 #pragma unroll
-    for (int s = 0; s < NST; ++s)
-#pragma unroll
-        for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-            for (int n1 = 0; n1 < R1; ++n1)
-                v[s][jj * R1 + n1] = ld<S, NT>(ps[s] + (int64_t)(n1 * N2 + t + T * jj) * lg.sN);
-
-    // gradient accumulators of the reverse sweep: the potential marginal
-    // Im(conj(lambda) psi) on the side of the potential factor the pass is told
-    // to take it (before: G_MIN, after: G_MOUT), and the dL/dB term of the x
-    // kinetic factor in reciprocal space
-    double gm_acc = 0.0, gb_acc = 0.0;
-    if constexpr (NST == 2) {
-        if (a.gflags & G_MIN) {
-#pragma unroll
-            for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
+                for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
+            }
         }
-    }
+        auto potential = [&]() {
+            if constexpr (VK == 1) {
+                const LineTables<AXIS> tb(a, lg, t);
+#pragma unroll
+                for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+                    for (int n1 = 0; n1 < R1; ++n1) {
+                        const double2 f = tb.at(n1 * N2 + T * jj, a.kconj);
+#pragma unroll
+                        for (int s = 0; s < NST; ++s) v[s][jj * R1 + n1] = cmul(v[s][jj * R1 + n1], f);
+                    }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < JA; ++jj)
+#pragma unroll
+                    for (int n1 = 0; n1 < R1; ++n1) {
+                        int c[4];
+                        elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, n1 * N2 + t + T * jj, c);
+                        const double2 f = vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
+#pragma unroll
+                        for (int s = 0; s < NST; ++s) v[s][jj * R1 + n1] = cmul(v[s][jj * R1 + n1], f);
+                    }
+            }
+        };
+        if (VK != 0 && a.vmode == 1) potential();
 
-    auto potential = [&]() {
-        if constexpr (VK == 1) {
-            const LineTables<AXIS> tb(a, lg, t);
+        // ---- stage A (forward)
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int jj = 0; jj < JA; ++jj) {
+                const int jc = t + T * jj;
+                dft<R1, -1>(&v[s][jj * R1]);
+#pragma unroll
+                for (int k1 = 1; k1 < R1; ++k1) v[s][jj * R1 + k1] = cmul(v[s][jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) Lw(s, k1 * N2 + jc, v[s][jj * R1 + k1]);
+            }
+        sync();
+
+        // ---- stage B1 (forward), in place on its positions
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int ii = 0; ii < G1; ++ii) {
+                const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
+#pragma unroll
+                for (int n2 = 0; n2 < R2; ++n2) v[s][ii * R2 + n2] = Lr(s, k1 * N2 + n2 * R3 + j3);
+                dft<R2, -1>(&v[s][ii * R2]);
+#pragma unroll
+                for (int k2 = 1; k2 < R2; ++k2) v[s][ii * R2 + k2] = cmul(v[s][ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) Lw(s, k1 * N2 + k2 * R3 + j3, v[s][ii * R2 + k2]);
+            }
+        sync();
+
+        // ---- stage B2: forward, kinetic phase at k = k1 + R1 (k2 + R2 k3), inverse
+        // x kinetic factor table: y-major [y][k] on the x1 pass, k-major [k][y] on the x2 pass
+        const int yrow = (AXIS == AX_X1) ? lg.j1 : ((AXIS == AX_X2) ? lg.j2 : 0);
+        const double2* kt = a.ktab + (AXIS == AX_X1 ? (int64_t)yrow * N : (int64_t)yrow);
+        const int64_t kstride = AXIS == AX_X1 ? 1 : a.ny;
+        constexpr bool GB = (NST == 2) && (AXIS == AX_X1 || AXIS == AX_X2);
+        const bool gb_on = GB && (a.gflags & G_GB);
+        const double yv = a.y0 + a.ystep * yrow;
+        const double shift = yv * a.b_eoh;
+#pragma unroll
+        for (int ii = 0; ii < G2; ++ii) {
+            const int q = t + T * ii, k1 = q / R2, k2 = q % R2;
+#pragma unroll
+            for (int s = 0; s < NST; ++s) {
+#pragma unroll
+                for (int j3 = 0; j3 < R3; ++j3) v[s][ii * R3 + j3] = Lr(s, k1 * N2 + k2 * R3 + j3);
+                dft<R3, -1>(&v[s][ii * R3]);
+            }
+#pragma unroll
+            for (int k3 = 0; k3 < R3; ++k3) {
+                const int k = k1 + R1 * (k2 + R2 * k3);
+                if constexpr (GB) {
+                    if (gb_on) {
+                        // d theta_X / dB at (k, y), on the values before the kinetic factor
+                        const int m = (k < (N + 1) / 2) ? k : k - N;
+                        const double dth = a.db_coef * (a.kstep * m - shift) * yv;
+                        gb_acc += dth * im_cl_p(v[1][ii * R3 + k3], v[0][ii * R3 + k3]);
+                    }
+                }
+                double2 f;
+                if constexpr (KT_LDS) {
+                    f = twl[N + k];
+                } else {
+                    f = kt[k * kstride];
+                    if (a.kconj) f = conjd(f);
+                }
+#pragma unroll
+                for (int s = 0; s < NST; ++s) v[s][ii * R3 + k3] = cmul(v[s][ii * R3 + k3], f);
+            }
+#pragma unroll
+            for (int s = 0; s < NST; ++s) {
+                dft<R3, 1>(&v[s][ii * R3]);
+#pragma unroll
+                for (int j3 = 0; j3 < R3; ++j3) Lw(s, k1 * N2 + k2 * R3 + j3, v[s][ii * R3 + j3]);
+            }
+        }
+        sync();
+
+        // ---- stage B1 (inverse)
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int ii = 0; ii < G1; ++ii) {
+                const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) v[s][ii * R2 + k2] = Lr(s, k1 * N2 + k2 * R3 + j3);
+#pragma unroll
+                for (int k2 = 1; k2 < R2; ++k2) v[s][ii * R2 + k2] = cmulc(v[s][ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
+                dft<R2, 1>(&v[s][ii * R2]);
+#pragma unroll
+                for (int n2 = 0; n2 < R2; ++n2) Lw(s, k1 * N2 + n2 * R3 + j3, v[s][ii * R2 + n2]);
+            }
+        sync();
+
+        // ---- stage A (inverse), back on the loaded elements
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int jj = 0; jj < JA; ++jj) {
+                const int jc = t + T * jj;
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) v[s][jj * R1 + k1] = Lr(s, k1 * N2 + jc);
+#pragma unroll
+                for (int k1 = 1; k1 < R1; ++k1) v[s][jj * R1 + k1] = cmulc(v[s][jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
+                dft<R1, 1>(&v[s][jj * R1]);
+            }
+
+        if (VK != 0 && a.vmode == 2) potential();
+
+        if constexpr (NST == 2) {
+            if (a.gflags & G_MOUT) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
+            }
+        }
+
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
 #pragma unroll
             for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1) {
-                    const double2 f = tb.at(n1 * N2 + T * jj, a.kconj);
-#pragma unroll
-                    for (int s = 0; s < NST; ++s) v[s][jj * R1 + n1] = cmul(v[s][jj * R1 + n1], f);
+                for (int n1 = 0; n1 < R1; ++n1)
+                    st<S, NT>(ps[s] + elem_off(lg, jj, n1), v[s][jj * R1 + n1]);
+
+        if constexpr (NST == 2) {
+            // the same partial-sum layout as the two-stage pass: dL/dB per block; the
+            // marginal per line on the x1 and y1 axes (the line's threads summed in
+            // fixed order), per block on x2 and y2 (a block's lines share r1)
+            double* red = reinterpret_cast<double*>(lds_raw);
+            if (a.gflags & G_GB) {
+                const double sum = block_sum(gb_acc, red);
+                if (tid == 0) a.gb_part[blockIdx.x] += sum;
+            }
+            if (a.gflags & (G_MIN | G_MOUT)) {
+                if constexpr (AXIS == AX_X1 || AXIS == AX_Y1) {
+                    __syncthreads();
+                    red[t * W + cl] = gm_acc;
+                    __syncthreads();
+                    if (t == 0) {
+                        double sum = 0.0;
+                        for (int q = 0; q < T; ++q) sum += red[q * W + cl];
+                        a.marg_part[line] += sum;
+                    }
+                } else {
+                    const double sum = block_sum(gm_acc, red);
+                    if (tid == 0) a.marg_part[blockIdx.x] += sum;
                 }
-        } else {
-#pragma unroll
-            for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1) {
-                    int c[4];
-                    elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, n1 * N2 + t + T * jj, c);
-                    const double2 f = vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
-#pragma unroll
-                    for (int s = 0; s < NST; ++s) v[s][jj * R1 + n1] = cmul(v[s][jj * R1 + n1], f);
-                }
+            }
         }
     };
-    if (VK != 0 && a.vmode == 1) potential();
 
-    // ---- stage A (forward)
+    if constexpr (PERS) {
+        // persistent: tiles blockIdx.x, + gridDim.x, ...; the next tile's
+        // elements are loaded (as stored) before the current one is transformed
+        const uint32_t ntiles = a.ntiles;
+        S raw[E];
+        uint32_t tile = blockIdx.x;
+        if (tile < ntiles) {
+            const LineGeom<AXIS> lg(a, tile * (uint32_t)W + (uint32_t)cl);
+            const S* p = reinterpret_cast<const S*>(a.psi) + lg.base;
 #pragma unroll
-    for (int s = 0; s < NST; ++s)
+            for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
-        for (int jj = 0; jj < JA; ++jj) {
-            const int jc = t + T * jj;
-            dft<R1, -1>(&v[s][jj * R1]);
-#pragma unroll
-            for (int k1 = 1; k1 < R1; ++k1) v[s][jj * R1 + k1] = cmul(v[s][jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) Lw(s, k1 * N2 + jc, v[s][jj * R1 + k1]);
+                for (int n1 = 0; n1 < R1; ++n1) raw[jj * R1 + n1] = ld_raw<S, NT>(p + elem_off(lg, jj, n1));
         }
-    line_sync<AXIS, T>();
-
-    // ---- stage B1 (forward), in place on its positions
+        for (; tile < ntiles; tile += gridDim.x) {
+            // the thread's line slot and position index pass through an empty asm
+            // each tile, so that the LDS and table addresses derived from them are
+            // recomputed per tile rather than hoisted out of the loop and held in
+            // registers for all of it
+            asm volatile("" : "+v"(t), "+v"(cl));
+            const uint32_t line = tile * (uint32_t)W + (uint32_t)cl;
+            const LineGeom<AXIS> lg(a, line);
+            S* ps[1] = {reinterpret_cast<S*>(a.psi) + lg.base};
 #pragma unroll
-    for (int s = 0; s < NST; ++s)
+            for (int e = 0; e < E; ++e) v[0][e] = widen(raw[e]);
+            const uint32_t next = tile + gridDim.x;
+            if (next < ntiles) {
+                const LineGeom<AXIS> ln(a, next * (uint32_t)W + (uint32_t)cl);
+                const S* p = reinterpret_cast<const S*>(a.psi) + ln.base;
 #pragma unroll
-        for (int ii = 0; ii < G1; ++ii) {
-            const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
+                for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
-            for (int n2 = 0; n2 < R2; ++n2) v[s][ii * R2 + n2] = Lr(s, k1 * N2 + n2 * R3 + j3);
-            dft<R2, -1>(&v[s][ii * R2]);
-#pragma unroll
-            for (int k2 = 1; k2 < R2; ++k2) v[s][ii * R2 + k2] = cmul(v[s][ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
-#pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) Lw(s, k1 * N2 + k2 * R3 + j3, v[s][ii * R2 + k2]);
-        }
-    line_sync<AXIS, T>();
-
-    // ---- stage B2: forward, kinetic phase at k = k1 + R1 (k2 + R2 k3), inverse
-    // x kinetic factor table: y-major [y][k] on the x1 pass, k-major [k][y] on the x2 pass
-    const int yrow = (AXIS == AX_X1) ? lg.j1 : ((AXIS == AX_X2) ? lg.j2 : 0);
-    const double2* kt = a.ktab + (AXIS == AX_X1 ? (int64_t)yrow * N : (int64_t)yrow);
-    const int64_t kstride = AXIS == AX_X1 ? 1 : a.ny;
-    constexpr bool GB = (NST == 2) && (AXIS == AX_X1 || AXIS == AX_X2);
-    const bool gb_on = GB && (a.gflags & G_GB);
-    const double yv = a.y0 + a.ystep * yrow;
-    const double shift = yv * a.b_eoh;
-#pragma unroll
-    for (int ii = 0; ii < G2; ++ii) {
-        const int q = t + T * ii, k1 = q / R2, k2 = q % R2;
-#pragma unroll
-        for (int s = 0; s < NST; ++s) {
-#pragma unroll
-            for (int j3 = 0; j3 < R3; ++j3) v[s][ii * R3 + j3] = Lr(s, k1 * N2 + k2 * R3 + j3);
-            dft<R3, -1>(&v[s][ii * R3]);
-        }
-#pragma unroll
-        for (int k3 = 0; k3 < R3; ++k3) {
-            const int k = k1 + R1 * (k2 + R2 * k3);
-            if constexpr (GB) {
-                if (gb_on) {
-                    // d theta_X / dB at (k, y), on the values before the kinetic factor
-                    const int m = (k < (N + 1) / 2) ? k : k - N;
-                    const double dth = a.db_coef * (a.kstep * m - shift) * yv;
-                    gb_acc += dth * im_cl_p(v[1][ii * R3 + k3], v[0][ii * R3 + k3]);
-                }
+                    for (int n1 = 0; n1 < R1; ++n1) raw[jj * R1 + n1] = ld_raw<S, NT>(p + elem_off(ln, jj, n1));
             }
-            double2 f;
-            if constexpr (KT_LDS) {
-                f = twl[N + k];
-            } else {
-                f = kt[k * kstride];
-                if (a.kconj) f = conjd(f);
-            }
-#pragma unroll
-            for (int s = 0; s < NST; ++s) v[s][ii * R3 + k3] = cmul(v[s][ii * R3 + k3], f);
+            round_trip(lg, line, ps);
         }
+    } else {
+        const uint32_t line = blockIdx.x * (uint32_t)W + (uint32_t)cl;
+        const LineGeom<AXIS> lg(a, line);
+        // the state, and in the reverse sweep the adjoint state beside it
+        S* ps[NST];
+        ps[0] = reinterpret_cast<S*>(a.psi) + lg.base;
+        if constexpr (NST == 2) ps[1] = reinterpret_cast<S*>(a.lam) + lg.base;
 #pragma unroll
-        for (int s = 0; s < NST; ++s) {
-            dft<R3, 1>(&v[s][ii * R3]);
+        for (int s = 0; s < NST; ++s)
 #pragma unroll
-            for (int j3 = 0; j3 < R3; ++j3) Lw(s, k1 * N2 + k2 * R3 + j3, v[s][ii * R3 + j3]);
-        }
-    }
-    line_sync<AXIS, T>();
-
-    // ---- stage B1 (inverse)
+            for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
-    for (int s = 0; s < NST; ++s)
-#pragma unroll
-        for (int ii = 0; ii < G1; ++ii) {
-            const int q = t + T * ii, k1 = q / R3, j3 = q % R3;
-#pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) v[s][ii * R2 + k2] = Lr(s, k1 * N2 + k2 * R3 + j3);
-#pragma unroll
-            for (int k2 = 1; k2 < R2; ++k2) v[s][ii * R2 + k2] = cmulc(v[s][ii * R2 + k2], twl[(uint32_t)(R1 * j3 * k2) % N]);
-            dft<R2, 1>(&v[s][ii * R2]);
-#pragma unroll
-            for (int n2 = 0; n2 < R2; ++n2) Lw(s, k1 * N2 + n2 * R3 + j3, v[s][ii * R2 + n2]);
-        }
-    line_sync<AXIS, T>();
-
-    // ---- stage A (inverse), back on the loaded elements
-#pragma unroll
-    for (int s = 0; s < NST; ++s)
-#pragma unroll
-        for (int jj = 0; jj < JA; ++jj) {
-            const int jc = t + T * jj;
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) v[s][jj * R1 + k1] = Lr(s, k1 * N2 + jc);
-#pragma unroll
-            for (int k1 = 1; k1 < R1; ++k1) v[s][jj * R1 + k1] = cmulc(v[s][jj * R1 + k1], twl[(uint32_t)(jc * k1) % N]);
-            dft<R1, 1>(&v[s][jj * R1]);
-        }
-
-    if (VK != 0 && a.vmode == 2) potential();
-
-    if constexpr (NST == 2) {
-        if (a.gflags & G_MOUT) {
-#pragma unroll
-            for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
-        }
-    }
-
-#pragma unroll
-    for (int s = 0; s < NST; ++s)
-#pragma unroll
-        for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-            for (int n1 = 0; n1 < R1; ++n1)
-                st<S, NT>(ps[s] + (int64_t)(n1 * N2 + t + T * jj) * lg.sN, v[s][jj * R1 + n1]);
-
-    if constexpr (NST == 2) {
-        // the same partial-sum layout as the two-stage pass: dL/dB per block; the
-        // marginal per line on the x1 and y1 axes (the line's threads summed in
-        // fixed order), per block on x2 and y2 (a block's lines share r1)
-        double* red = reinterpret_cast<double*>(lds_raw);
-        if (a.gflags & G_GB) {
-            const double sum = block_sum(gb_acc, red);
-            if (tid == 0) a.gb_part[blockIdx.x] += sum;
-        }
-        if (a.gflags & (G_MIN | G_MOUT)) {
-            if constexpr (AXIS == AX_X1 || AXIS == AX_Y1) {
-                __syncthreads();
-                red[t * W + cl] = gm_acc;
-                __syncthreads();
-                if (t == 0) {
-                    double sum = 0.0;
-                    for (int q = 0; q < T; ++q) sum += red[q * W + cl];
-                    a.marg_part[line] += sum;
-                }
-            } else {
-                const double sum = block_sum(gm_acc, red);
-                if (tid == 0) a.marg_part[blockIdx.x] += sum;
-            }
-        }
+                for (int n1 = 0; n1 < R1; ++n1) v[s][jj * R1 + n1] = ld<S, NT>(ps[s] + elem_off(lg, jj, n1));
+        round_trip(lg, line, ps);
     }
 }
 
 // Three-stage factorisations: n = R1 R2 R3 on T threads per line.
-template <class S, int AXIS, int NST, int VK, bool NT>
+template <class S, int AXIS, int NST, int VK, bool NT, bool PERS = false>
 AxisKernel pick3(int n, int* t) {
     switch (n) {
-        case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, NST, VK, NT>;
-        case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, NST, VK, NT>;
-        case 256: *t = 32; return k_axis3<S, AXIS, 8, 8, 4, 32, NST, VK, NT>;
+        case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, NST, VK, NT, PERS>;
+        case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, NST, VK, NT, PERS>;
+        case 256: *t = 32; return k_axis3<S, AXIS, 8, 8, 4, 32, NST, VK, NT, PERS>;
         default: *t = 0; return nullptr;
     }
 }
@@ -298,8 +397,15 @@ AxisKernel pick3(int n, int* t) {
 // Forward single-state passes: the x1 pass carries no potential factor, the
 // y2 pass always carries it, x2 and y1 either.  Reverse dual-state passes: the
 // x passes carry none, y1 (before its transform) and y2 (after) carry it.
+// Persistent forms: the x1 and y1 passes without a potential factor.
 template <class S, bool NT>
-AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, int* t) {
+AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, bool pers, int* t) {
+    if (pers) {
+        if (nst == 1 && vk == 0 && axis == AX_X1) return pick3<S, AX_X1, 1, 0, NT, true>(n, t);
+        if (nst == 1 && vk == 0 && axis == AX_Y1) return pick3<S, AX_Y1, 1, 0, NT, true>(n, t);
+        *t = 0;
+        return nullptr;
+    }
     if (nst == 2) {
         switch (axis) {
             case AX_X1:
@@ -346,8 +452,8 @@ AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, int* t) {
 }
 
 template <class S>
-AxisKernel pick_axis3(int axis, int n, int vk, int nst, bool nt, int* t) {
-    return nt ? pick_axis3_nt<S, true>(axis, n, vk, nst, t) : pick_axis3_nt<S, false>(axis, n, vk, nst, t);
+AxisKernel pick_axis3(int axis, int n, int vk, int nst, bool nt, bool pers, int* t) {
+    return nt ? pick_axis3_nt<S, true>(axis, n, vk, nst, pers, t) : pick_axis3_nt<S, false>(axis, n, vk, nst, pers, t);
 }
 
 }  // namespace dev

@@ -24,6 +24,7 @@ struct PassArgs {
     void* lam;                // adjoint state (dual-state passes only)
     int nx, ny;
     int W;                    // lines per block
+    uint32_t ntiles;          // tiles of W lines (nlines / W); a persistent pass's grid may be smaller
     int kconj;                // use conj(ktab) and conj(potential factor): reverse sweep
     const double2* tw;        // twiddles exp(-2 pi i j / n), j < n
     const double2* ktab;      // k-space factor incl. 1/n: x1 pass [ny][nx], x2 and plane passes [nx][ny], y [ny]
@@ -88,8 +89,10 @@ __host__ __device__ constexpr size_t axis3_lds_bytes(int n, int w, int nst, bool
     return axis3_xchg_bytes(n, w, nst, c64) + 2u * (size_t)n * 16u;
 }
 
-// Launch one per-axis pass: blocks of t*W threads, nlines/W blocks.
-hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, int64_t nlines,
+// Launch one per-axis pass: blocks of t*W threads, nlines/W blocks; with pers
+// (three-stage forward x1 and y1 passes only) the persistent form, as many
+// blocks as fit the device at once, walking the a.ntiles = nlines/W tiles.
+hipError_t launch_axis(int axis, int n, bool mixed, int nst, bool pers, const PassArgs& a, int64_t nlines,
                        size_t lds_bytes, hipStream_t s);
 
 // Fused (x2, y2)-plane pass: X2(ktab) -> potential factor -> Y2(ktab2), one

@@ -20,7 +20,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <unordered_set>
 
 #include "axis_pass.hpp"
@@ -35,8 +38,8 @@ AxisKernel pick_axis_f64_1(int axis, int n, int vk, bool nt, int* t);
 AxisKernel pick_axis_f64_2(int axis, int n, int vk, bool nt, int* t);
 AxisKernel pick_axis_f32_1(int axis, int n, int vk, bool nt, int* t);
 AxisKernel pick_axis_f32_2(int axis, int n, int vk, bool nt, int* t);
-AxisKernel pick_axis3_f64(int axis, int n, int vk, int nst, bool nt, int* t);
-AxisKernel pick_axis3_f32(int axis, int n, int vk, int nst, bool nt, int* t);
+AxisKernel pick_axis3_f64(int axis, int n, int vk, int nst, bool nt, bool pers, int* t);
+AxisKernel pick_axis3_f32(int axis, int n, int vk, int nst, bool nt, bool pers, int* t);
 AxisKernel pick_plane_f64(int nx, int ny, int vk, int* nt);
 AxisKernel pick_plane_f32(int nx, int ny, int vk, int* nt);
 
@@ -235,14 +238,40 @@ bool fft_shape(int n, FftShape* out) {
     }
 }
 
-hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, int64_t nlines, size_t lds_bytes,
-                       hipStream_t s) {
+// Blocks of fn (threads, dynamic LDS) resident on the whole device at once:
+// blocks per CU times the CU count, cached per kernel and shape.
+hipError_t resident_blocks(AxisKernel fn, int threads, size_t lds_bytes, int* out) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void*, int, size_t>, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(reinterpret_cast<const void*>(fn), threads, lds_bytes);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), threads,
+                                                         lds_bytes);
+    if (e != hipSuccess) return e;
+    *out = per_cu * cus;
+    cache[key] = *out;
+    return hipSuccess;
+}
+
+hipError_t launch_axis(int axis, int n, bool mixed, int nst, bool pers, const PassArgs& a, int64_t nlines,
+                       size_t lds_bytes, hipStream_t s) {
     int t = 0;
     AxisKernel fn = nullptr;
     const int vk = a.vmode == 0 ? 0 : (a.vdirect ? 2 : 1);
     const bool nt = a.nt != 0;
     if (axis3_threads(n, nst) > 0)
-        fn = mixed ? pick_axis3_f32(axis, n, vk, nst, nt, &t) : pick_axis3_f64(axis, n, vk, nst, nt, &t);
+        fn = mixed ? pick_axis3_f32(axis, n, vk, nst, nt, pers, &t) : pick_axis3_f64(axis, n, vk, nst, nt, pers, &t);
+    else if (pers)
+        return hipErrorInvalidValue;  // only the three-stage passes have a persistent form
     else if (!mixed)
         fn = (nst == 2) ? pick_axis_f64_2(axis, n, vk, nt, &t) : pick_axis_f64_1(axis, n, vk, nt, &t);
     else
@@ -271,7 +300,17 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, const PassArgs& a, 
             raised.insert(key);
         }
     }
-    hipLaunchKernelGGL(fn, dim3((unsigned)nblocks), dim3(t * a.W), lds_bytes, s, a);
+    int64_t grid = nblocks;
+    if (pers) {
+        // persistent pass: the blocks that fit the device at once walk the
+        // a.ntiles tiles
+        if (a.ntiles != (uint32_t)nblocks) return hipErrorInvalidValue;
+        int resident = 0;
+        hipError_t e = resident_blocks(fn, t * a.W, lds_bytes, &resident);
+        if (e != hipSuccess) return e;
+        if (resident > 0) grid = std::min<int64_t>(nblocks, resident);
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(t * a.W), lds_bytes, s, a);
     return hipGetLastError();
 }
 
