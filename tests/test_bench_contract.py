@@ -22,7 +22,7 @@ def test_more_than_one_gpu_is_refused():
 def test_bench_line_fields():
     steps, warmup = 20, 2
     r = subprocess.run([sys.executable, "bench.py", "--steps", str(steps), "--warmup", str(warmup),
-                        "--no-mixed", "--no-extras", "--cpu-budget", "2"],
+                        "--no-compare", "--no-extras", "--cpu-budget", "2"],
                        cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
@@ -36,7 +36,9 @@ def test_bench_line_fields():
     assert d["unit"] == "gp-steps/s" and d["value"] > 0.0
     # value is grid-point-steps per second of the timed steps
     assert abs(d["value"] - d["config"]["points"] * 1e3 / d["ms_per_step"]) <= 1e-9 * d["value"]
-    assert "workload" in d["config"] and d["config"]["points"] == 64 ** 4
+    # the default workload: 256x128 per electron in complex64 storage
+    assert "workload" in d["config"] and d["config"]["points"] == (256 * 128) ** 2
+    assert d["config"]["precision"] == "mixed" and d["dtype"] == "f64"
     rl = d["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rl, k
@@ -44,6 +46,8 @@ def test_bench_line_fields():
     assert abs(rl["frac"] - rl["achieved"] / rl["peak"]) <= 1e-12
     # achieved = algorithmic bytes of one launch over the average launch duration
     assert abs(rl["achieved"] - rl["algorithmic_bytes_per_launch"] / rl["avg_launch_s"] / 1e9) <= 1e-9 * rl["achieved"]
-    assert rl["launches_timed"] == steps        # one plane pass per step in the timed repeat
+    # four passes per step; the x passes also take the opening half step
+    assert d["config"]["passes_per_step"] == 4
+    assert steps <= rl["launches_timed"] <= steps + 1
     cpu = d["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["value"] > 0.0 and cpu["cores"] >= 1
