@@ -67,25 +67,6 @@ __device__ __forceinline__ void lds_barrier() {
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// State element as stored (complex128 or complex64), no widening: the
-// prefetch registers of the persistent passes hold the next tile this way.
-template <class S, bool NT>
-__device__ __forceinline__ S ld_raw(const S* p) {
-    if constexpr (NT) {
-        if constexpr (std::is_same<S, double2>::value) {
-            const ntv_d2 r = __builtin_nontemporal_load(reinterpret_cast<const ntv_d2*>(p));
-            return make_double2(r.x, r.y);
-        } else {
-            const ntv_f2 r = __builtin_nontemporal_load(reinterpret_cast<const ntv_f2*>(p));
-            return make_float2(r.x, r.y);
-        }
-    } else {
-        return *p;
-    }
-}
-__device__ __forceinline__ double2 widen(double2 v) { return v; }
-__device__ __forceinline__ double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
-
 template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT, bool PERS>
 __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !std::is_same<S, double2>::value)) k_axis3(const PassArgs a) {
     static_assert(!PERS || NST == 1, "only the forward passes are persistent");
@@ -153,28 +134,36 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 for (int e = 0; e < E; ++e) gm_acc += im_cl_p(v[1][e], v[0][e]);
             }
         }
+        // the potential factor on the thread's elements (element e = jj R1 + n1 at
+        // line position n1 N2 + t + T jj), its table entries loaded in batches
         auto potential = [&]() {
             if constexpr (VK == 1) {
                 const LineTables<AXIS> tb(a, lg, t);
+                const double2 f0 = tb.fixed();
+                batched<E, 4>([&](int e) { return tb.load((e % R1) * N2 + T * (e / R1)); },
+                              [&](int e, const VLoad& l) {
+                                  const double2 f = tb.combine(f0, l, a.kconj);
 #pragma unroll
-                for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-                    for (int n1 = 0; n1 < R1; ++n1) {
-                        const double2 f = tb.at(n1 * N2 + T * jj, a.kconj);
-#pragma unroll
-                        for (int s = 0; s < NST; ++s) v[s][jj * R1 + n1] = cmul(v[s][jj * R1 + n1], f);
-                    }
+                                  for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
+                              });
             } else {
-#pragma unroll
-                for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-                    for (int n1 = 0; n1 < R1; ++n1) {
+                constexpr int VKF = VK == 0 ? 1 : VK;
+                auto coords = [&](int e, int* c) {
+                    elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, (e % R1) * N2 + t + T * (e / R1), c);
+                };
+                batched<E, vbatch<VKF>()>(
+                    [&](int e) {
                         int c[4];
-                        elem_coord<AXIS>(lg.i1, lg.j1, lg.i2, lg.j2, n1 * N2 + t + T * jj, c);
-                        const double2 f = vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
+                        coords(e, c);
+                        return vload<VKF>(a, c[0], c[1], c[2], c[3]);
+                    },
+                    [&](int e, const VLoad& l) {
+                        int c[4];
+                        coords(e, c);
+                        const double2 f = vcombine<VKF>(a, l, c[0], c[1], c[2], c[3]);
 #pragma unroll
-                        for (int s = 0; s < NST; ++s) v[s][jj * R1 + n1] = cmul(v[s][jj * R1 + n1], f);
-                    }
+                        for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
+                    });
             }
         };
         if (VK != 0 && a.vmode == 1) potential();
@@ -221,6 +210,14 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
 #pragma unroll
         for (int ii = 0; ii < G2; ++ii) {
             const int q = t + T * ii, k1 = q / R2, k2 = q % R2;
+            // x axes: the group's kinetic factors come from the L2-resident table;
+            // their loads are issued ahead of the LDS reads and the DFT, which hide them
+            double2 kf[R3];
+            if constexpr (!KT_LDS) {
+#pragma unroll
+                for (int k3 = 0; k3 < R3; ++k3) kf[k3] = kt[(k1 + R1 * (k2 + R2 * k3)) * kstride];
+                after_loads();
+            }
 #pragma unroll
             for (int s = 0; s < NST; ++s) {
 #pragma unroll
@@ -242,7 +239,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 if constexpr (KT_LDS) {
                     f = twl[N + k];
                 } else {
-                    f = kt[k * kstride];
+                    f = kf[k3];
                     if (a.kconj) f = conjd(f);
                 }
 #pragma unroll
@@ -373,12 +370,18 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         S* ps[NST];
         ps[0] = reinterpret_cast<S*>(a.psi) + lg.base;
         if constexpr (NST == 2) ps[1] = reinterpret_cast<S*>(a.lam) + lg.base;
+        S raw[NST][E];
 #pragma unroll
         for (int s = 0; s < NST; ++s)
 #pragma unroll
             for (int jj = 0; jj < JA; ++jj)
 #pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1) v[s][jj * R1 + n1] = ld<S, NT>(ps[s] + elem_off(lg, jj, n1));
+                for (int n1 = 0; n1 < R1; ++n1) raw[s][jj * R1 + n1] = ld_raw<S, NT>(ps[s] + elem_off(lg, jj, n1));
+        after_loads();
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[s][e] = widen(raw[s][e]);
         round_trip(lg, line, ps);
     }
 }

@@ -64,6 +64,26 @@ __device__ __forceinline__ void st(S* p, double2 v) {
     }
 }
 
+// State element as stored (complex128 or complex64), not widened: loads of a
+// batch land here first, and the persistent passes' prefetch registers hold
+// the next tile this way.
+template <class S, bool NT>
+__device__ __forceinline__ S ld_raw(const S* p) {
+    if constexpr (NT) {
+        if constexpr (std::is_same<S, double2>::value) {
+            const ntv_d2 r = __builtin_nontemporal_load(reinterpret_cast<const ntv_d2*>(p));
+            return make_double2(r.x, r.y);
+        } else {
+            const ntv_f2 r = __builtin_nontemporal_load(reinterpret_cast<const ntv_f2*>(p));
+            return make_float2(r.x, r.y);
+        }
+    } else {
+        return *p;
+    }
+}
+__device__ __forceinline__ double2 widen(double2 v) { return v; }
+__device__ __forceinline__ double2 widen(float2 v) { return make_double2((double)v.x, (double)v.y); }
+
 // Element type of an LDS exchange of the state: complex64 with complex64
 // storage (the exchange rounds like one more store of the state), complex128
 // otherwise.  The arithmetic is FP64 either way.
@@ -96,20 +116,65 @@ __device__ __forceinline__ double reduce_2pi(double th) {
     return fma(-q, c3, fma(-q, c2, fma(-q, c1, th)));
 }
 
-// exp(-i tau (V(r1) + V(r2) + V12(r1 - r2)) / hbar), or its conjugate.
-// VK = 1: product of the one-body and two-body factor tables; VK = 2: the FP64
-// angle evaluated here, reduced mod 2 pi, then sincos; VK = 3: as VK = 1
-// without the one-body factor of electron 1 (applied by the caller).
+// Every load of a batch is issued before any of its values is used.  Left
+// alone, the machine scheduler places each loaded value's first use right after
+// its load, behind a wait for that load (s_waitcnt vmcnt(0)), so a wave keeps a
+// single load in flight; this scheduling barrier keeps a batch's loads ahead of
+// their uses, which then wait for the whole batch once.
+__device__ __forceinline__ void after_loads() { __builtin_amdgcn_sched_barrier(0); }
+
+// Apply use(e, load(e)) to the elements e = 0 .. E-1 in batches of G: the G
+// loads of a batch are issued, then their G uses run.
+template <int E, int G, class Load, class Use>
+__device__ __forceinline__ void batched(Load load, Use use) {
+#pragma unroll
+    for (int b = 0; b < E; b += G) {
+        decltype(load(0)) buf[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+            if (b + i < E) buf[i] = load(b + i);
+        after_loads();
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+            if (b + i < E) use(b + i, buf[i]);
+    }
+}
+
+// Table entries / potential values one element's potential factor needs,
+// loaded ahead of use (vload) and combined later (vcombine).  Table form
+// (VK = 1, 3): p = a1(r1) (VK = 1 only), q = a1(r2), r = ac(r1 - r2); per-point
+// form (VK = 2): p = (V(r1), V(r2)).
+struct VLoad {
+    double2 p, q, r;
+};
+
 template <int VK>
-__device__ __forceinline__ double2 vfactor(const PassArgs& a, int i1, int j1, int i2, int j2) {
+__device__ __forceinline__ VLoad vload(const PassArgs& a, int i1, int j1, int i2, int j2) {
+    VLoad l;
+    if constexpr (VK == 1 || VK == 3) {
+        l.q = a.a1[i2 * a.ny + j2];
+        if constexpr (VK == 1) l.p = a.a1[i1 * a.ny + j1];
+        if (a.ac) l.r = a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)];
+    } else {
+        l.p = make_double2(a.vtab[i1 * a.ny + j1], a.vtab[i2 * a.ny + j2]);
+    }
+    return l;
+}
+
+// exp(-i tau (V(r1) + V(r2) + V12(r1 - r2)) / hbar), or its conjugate, from the
+// loaded entries.  VK = 1: product of the one-body and two-body factor tables;
+// VK = 2: the FP64 angle evaluated here, reduced mod 2 pi, then sincos; VK = 3:
+// as VK = 1 without the one-body factor of electron 1 (applied by the caller).
+template <int VK>
+__device__ __forceinline__ double2 vcombine(const PassArgs& a, const VLoad& l, int i1, int j1, int i2, int j2) {
     double2 f;
     if constexpr (VK == 1 || VK == 3) {
-        f = a.a1[i2 * a.ny + j2];
-        if constexpr (VK == 1) f = cmul(a.a1[i1 * a.ny + j1], f);
-        if (a.ac) f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)]);
+        f = l.q;
+        if constexpr (VK == 1) f = cmul(l.p, f);
+        if (a.ac) f = cmul(f, l.r);
         if (a.kconj) f = conjd(f);
     } else {
-        double v = a.vtab[i1 * a.ny + j1] + a.vtab[i2 * a.ny + j2];
+        double v = l.p.x + l.p.y;
         if (a.ck != 0.0) {
             const double ddx = (double)(i1 - i2) * a.dx;
             const double ddy = (double)(j1 - j2) * a.dy;
@@ -125,6 +190,30 @@ __device__ __forceinline__ double2 vfactor(const PassArgs& a, int i1, int j1, in
     }
     return f;
 }
+
+// The same factor with its table entries loaded in place (the fused plane pass
+// applies it element by element inside its LDS stages; there the batched form
+// measured slower: 64x64 FP64 plane pass 104 -> 130 VGPRs, 127 -> 163 us).
+template <int VK>
+__device__ __forceinline__ double2 vfactor(const PassArgs& a, int i1, int j1, int i2, int j2) {
+    double2 f;
+    if constexpr (VK == 1 || VK == 3) {
+        f = a.a1[i2 * a.ny + j2];
+        if constexpr (VK == 1) f = cmul(a.a1[i1 * a.ny + j1], f);
+        if (a.ac) f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)]);
+        if (a.kconj) f = conjd(f);
+    } else {
+        VLoad l;
+        l.p = make_double2(a.vtab[i1 * a.ny + j1], a.vtab[i2 * a.ny + j2]);
+        f = vcombine<VK>(a, l, i1, j1, i2, j2);
+    }
+    return f;
+}
+
+// Elements per batch of potential-factor loads: 4 with three complex table
+// entries per element (48 VGPRs in flight), 8 otherwise.
+template <int VK>
+constexpr int vbatch() { return VK == 1 ? 4 : 8; }
 
 // Synchronisation after an LDS exchange of a line pass.  Lines along y2 put a
 // line's T threads on consecutive lanes, so with T dividing 64 every wavefront
@@ -271,16 +360,40 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     }
     __syncthreads();
     const double2* twl = TWL;
-    // potential factor of element m of this line
-    auto pfactor = [&](int m) -> double2 {
+    double2 v[NST][E];  // the thread's elements of the state (and the adjoint state)
+    // line position of the thread's element e = jj * N1 + n1
+    auto pos = [&](int e) { return (e % N1) * N2 + t + T * (e / N1); };
+    // the potential factor on the thread's elements, its table entries loaded in batches
+    auto apply_potential = [&]() {
+        constexpr int VKF = VK == 0 ? 1 : VK;
         if constexpr (A1_LDS) {
-            double2 f = cmul(twl[2 * N + m], a.a1[i2 * a.ny + j2]);
-            if (a.ac) f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (m - j2 + a.ny - 1)]);
-            return a.kconj ? conjd(f) : f;
+            const double2 f2 = a.a1[i2 * a.ny + j2];  // electron 2's factor: the same along the line
+            batched<E, 8>(
+                [&](int e) {
+                    return a.ac ? a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (pos(e) - j2 + a.ny - 1)]
+                                : make_double2(1.0, 0.0);
+                },
+                [&](int e, double2 fc) {
+                    double2 f = cmul(twl[2 * N + pos(e)], f2);
+                    if (a.ac) f = cmul(f, fc);
+                    if (a.kconj) f = conjd(f);
+#pragma unroll
+                    for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
+                });
         } else {
-            int c[4];
-            elem_coord<AXIS>(i1, j1, i2, j2, m, c);
-            return vfactor<VK == 0 ? 1 : VK>(a, c[0], c[1], c[2], c[3]);
+            batched<E, vbatch<VKF>()>(
+                [&](int e) {
+                    int c[4];
+                    elem_coord<AXIS>(i1, j1, i2, j2, pos(e), c);
+                    return vload<VKF>(a, c[0], c[1], c[2], c[3]);
+                },
+                [&](int e, const VLoad& l) {
+                    int c[4];
+                    elem_coord<AXIS>(i1, j1, i2, j2, pos(e), c);
+                    const double2 f = vcombine<VKF>(a, l, c[0], c[1], c[2], c[3]);
+#pragma unroll
+                    for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
+                });
         }
     };
 
@@ -288,16 +401,23 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     ps[0] = reinterpret_cast<S*>(a.psi) + base;
     if constexpr (NST == 2) ps[1] = reinterpret_cast<S*>(a.lam) + base;
 
-    double2 v[NST][E];
+    {
+        S raw[NST][E];
 #pragma unroll
-    for (int jj = 0; jj < JA; ++jj) {
-        const int jc = t + T * jj;
+        for (int jj = 0; jj < JA; ++jj) {
+            const int jc = t + T * jj;
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) {
-            const int64_t off = (int64_t)(n1 * N2 + jc) * sN;
+            for (int n1 = 0; n1 < N1; ++n1) {
+                const int64_t off = (int64_t)(n1 * N2 + jc) * sN;
 #pragma unroll
-            for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = ld<S, NT>(ps[s] + off);
+                for (int s = 0; s < NST; ++s) raw[s][jj * N1 + n1] = ld_raw<S, NT>(ps[s] + off);
+            }
         }
+        after_loads();
+#pragma unroll
+        for (int s = 0; s < NST; ++s)
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[s][e] = widen(raw[s][e]);
     }
 
     double gm_acc = 0.0;  // marginal accumulator of this thread
@@ -309,17 +429,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         }
     }
 
-    if (VK != 0 && a.vmode == 1) {
-#pragma unroll
-        for (int jj = 0; jj < JA; ++jj) {
-#pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1) {
-                const double2 f = pfactor(n1 * N2 + t + T * jj);
-#pragma unroll
-                for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = cmul(v[s][jj * N1 + n1], f);
-            }
-        }
-    }
+    if (VK != 0 && a.vmode == 1) apply_potential();
 
     // ---- forward transform, stage A: DFT_n1 over n1 for each of the thread's columns
 #pragma unroll
@@ -380,21 +490,24 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
                 }
         }
     }
+    // element e = ii * N2 + k2 holds wave number t + T * ii + N1 * k2; on the x axes
+    // the kinetic factors come from the L2-resident table, loaded in one batch
+    auto wave_number = [&](int e) { return t + T * (e / N2) + N1 * (e % N2); };
+    if constexpr (KT_LDS) {
 #pragma unroll
-    for (int ii = 0; ii < IB; ++ii)
+        for (int e = 0; e < E; ++e) {
+            const double2 f = twl[N + wave_number(e)];
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) {
-            const int k = t + T * ii + N1 * k2;
-            double2 f;
-            if constexpr (KT_LDS) {
-                f = twl[N + k];
-            } else {
-                f = kt[k * kstride];
-                if (a.kconj) f = conjd(f);
-            }
-#pragma unroll
-            for (int s = 0; s < NST; ++s) v[s][ii * N2 + k2] = cmul(v[s][ii * N2 + k2], f);
+            for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
         }
+    } else {
+        batched<E, 8>([&](int e) { return kt[wave_number(e) * kstride]; },
+                      [&](int e, double2 f) {
+                          if (a.kconj) f = conjd(f);
+#pragma unroll
+                          for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
+                      });
+    }
 
     // ---- inverse transform: the forward network transposed
     if constexpr (N2 > 1) {
@@ -431,17 +544,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         }
     }
 
-    if (VK != 0 && a.vmode == 2) {
-#pragma unroll
-        for (int jj = 0; jj < JA; ++jj) {
-#pragma unroll
-            for (int n1 = 0; n1 < N1; ++n1) {
-                const double2 f = pfactor(n1 * N2 + t + T * jj);
-#pragma unroll
-                for (int s = 0; s < NST; ++s) v[s][jj * N1 + n1] = cmul(v[s][jj * N1 + n1], f);
-            }
-        }
-    }
+    if (VK != 0 && a.vmode == 2) apply_potential();
 
     if constexpr (NST == 2) {
         if (a.gflags & G_MOUT) {
@@ -510,14 +613,26 @@ struct LineTables {
         step = (AXIS == AX_X1 || AXIS == AX_X2) ? ny : 1;
         cstep = (AXIS == AX_X1) ? cy : (AXIS == AX_X2) ? -cy : (AXIS == AX_Y1) ? 1 : -1;
     }
-    __device__ __forceinline__ double2 at(int dm, bool conj) const {
-        const int64_t o = dm * step;
+    // the entry fixed along the line: the one-body factor of the electron the
+    // line does not move
+    __device__ __forceinline__ double2 fixed() const {
+        return (AXIS == AX_X1 || AXIS == AX_Y1) ? p2[0] : p1[0];
+    }
+    // the entries of element m0 + dm: the moving electron's one-body factor (q)
+    // and the two-body factor (r)
+    __device__ __forceinline__ VLoad load(int dm) const {
+        VLoad l;
+        l.q = (AXIS == AX_X1 || AXIS == AX_Y1) ? p1[dm * step] : p2[dm * step];
+        if (pc) l.r = pc[dm * cstep];
+        return l;
+    }
+    __device__ __forceinline__ double2 combine(double2 f0, const VLoad& l, bool conj) const {
         double2 f;
         if constexpr (AXIS == AX_X1 || AXIS == AX_Y1)
-            f = cmul(p1[o], p2[0]);
+            f = cmul(l.q, f0);
         else
-            f = cmul(p1[0], p2[o]);
-        if (pc) f = cmul(f, pc[dm * cstep]);
+            f = cmul(f0, l.q);
+        if (pc) f = cmul(f, l.r);
         return conj ? conjd(f) : f;
     }
 };
