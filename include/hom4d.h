@@ -244,6 +244,21 @@ int hom4d_grad_begin(hom4d* h, int32_t ckpt_every, void* d_pool, size_t pool_byt
 int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs,
                         void* d_lambda, double* loss, double* dL_dV, double* dL_dB);
 
+/* hom4d_grad_backward for callers that cannot allocate device memory: code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors, bit for bit the same outputs; it calls
+ * no hipMalloc, hipFree or allocating library routine.  The reverse sweep's
+ * FP64 partial sums go to a fixed 64 MiB array in device memory instead of a
+ * buffer the handle allocates on first use: one copy per GPU, shared by every
+ * handle on that GPU, its address taken by hom4d_create, kept until the
+ * process ends, cleared (by a fill kernel) at the start of every call.  Calls
+ * that overlap on one GPU race on it.  ENOMEM when the partial sums of the
+ * handle's grid exceed the array (8M doubles: grids up to 128x128 per
+ * electron fit, 256x128 does not); ESTATE also while pass timing is on (its
+ * event pool is created on demand). */
+int hom4d_grad_backward_noalloc(hom4d* h, const double* w_top, const double* coeffs, void* d_lambda,
+                                double* loss, double* dL_dV, double* dL_dB);
+
 /* Abandon an open recording. */
 int hom4d_grad_end(hom4d* h);
 

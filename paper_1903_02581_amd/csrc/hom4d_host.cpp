@@ -684,6 +684,95 @@ void free_all(hom4d* h) {
     if (h->host_out) (void)hipHostFree(h->host_out);
 }
 
+// Argument and state checks shared by the two reverse-sweep entry points.
+int grad_checks(hom4d* h, const double* w_top, const double* coeffs, void* d_lambda, double* loss, double* dL_dV,
+                double* dL_dB) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!coeffs || !d_lambda || !loss || !dL_dV || !dL_dB) return fail(HOM4D_EINVAL, "NULL argument");
+    if (((uintptr_t)d_lambda) % 16 != 0) return fail(HOM4D_EINVAL, "adjoint buffer must be 16-byte aligned");
+    int rc = check_weights(w_top, h->nxy);
+    if (rc) return rc;
+    if (!h->rec) return fail(HOM4D_ESTATE, "no recorded forward run (hom4d_grad_begin + hom4d_step)");
+    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
+    if ((size_t)(h->rec_steps / h->ckpt_every + 1) * h->state_bytes > h->pool_bytes)
+        return fail(HOM4D_ESTATE, "recorded checkpoints exceed the pool (%zu bytes)", h->pool_bytes);
+    return HOM4D_OK;
+}
+
+// Layout of the reverse sweep's FP64 partial sums: dL/dB per block of the two x
+// passes, the potential marginals per line (x1, y1) or per block (x2, y2), then
+// the finished dL/dV table.
+struct GradLayout {
+    int64_t nb_x1, nb_x2, nb_y2, len_m_x1, len_m_y1;
+    int w_x2, w_y2;
+    size_t total;  // doubles
+};
+
+GradLayout grad_layout(const hom4d* h) {
+    const hom4d_cfg& c = h->cfg;
+    const AxisPlan px1 = plan_axis(AX_X1, c.nx, c.ny, 2, true, h->mixed);
+    const AxisPlan px2 = plan_axis(AX_X2, c.nx, c.ny, 2, true, h->mixed);
+    const AxisPlan py1 = plan_axis(AX_Y1, c.nx, c.ny, 2, true, h->mixed);
+    const AxisPlan py2 = plan_axis(AX_Y2, c.nx, c.ny, 2, true, h->mixed);
+    GradLayout l;
+    l.nb_x1 = px1.nlines / px1.W;
+    l.nb_x2 = px2.nlines / px2.W;
+    l.nb_y2 = py2.nlines / py2.W;
+    l.len_m_x1 = px1.nlines;
+    l.len_m_y1 = py1.nlines;
+    l.w_x2 = px2.W;
+    l.w_y2 = py2.W;
+    l.total = (size_t)(l.nb_x1 + l.nb_x2 + l.len_m_x1 + l.len_m_y1 + l.nb_x2 + l.nb_y2 + h->nxy);
+    return l;
+}
+
+size_t grad_scratch_len(const hom4d* h) { return grad_layout(h).total; }
+
+// The reverse sweep on the partial-sum buffer buf (grad_scratch_len doubles, cleared here).
+int grad_sweep(hom4d* h, const double* w_top, const double* coeffs, void* d_lambda, double* loss, double* dL_dV,
+               double* dL_dB, double* buf) {
+    const hom4d_cfg& c = h->cfg;
+    const GradLayout l = grad_layout(h);
+    GradCtx g;
+    g.gb_x1 = buf;
+    g.gb_x2 = g.gb_x1 + l.nb_x1;
+    g.m_x1 = g.gb_x2 + l.nb_x2;
+    g.m_y1 = g.m_x1 + l.len_m_x1;
+    g.m_x2 = g.m_y1 + l.len_m_y1;
+    g.m_y2 = g.m_x2 + l.nb_x2;
+    double* dldv_dev = g.m_y2 + l.nb_y2;
+    int rc;
+    HIP_TRY(launch_zero(buf, (int64_t)l.total, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->w_dev, w_top, h->nxy * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(launch_loss_lambda(h->psi, d_lambda, h->mixed, h->w_dev, coeffs, h->nxy, h->red_part, h->red_blocks,
+                               h->stream));
+    double L = 0.0;
+    if ((rc = fetch_reduction(h, 1, &L))) return rc;
+    // reverse sweep, segment by segment, restoring the state at every checkpoint
+    int64_t seg_end = h->rec_steps;
+    for (int64_t k = h->rec_steps / h->ckpt_every; k >= 0; --k) {
+        const int64_t seg_start = k * h->ckpt_every;
+        if (seg_end > seg_start) {
+            if ((rc = run_steps(h, seg_end - seg_start, 2, d_lambda, true, &g))) return rc;
+        }
+        HIP_TRY(hipMemcpyAsync(h->psi, h->pool + (size_t)k * h->state_bytes, h->state_bytes, hipMemcpyDeviceToDevice,
+                               h->stream));
+        seg_end = seg_start;
+    }
+    HIP_TRY(launch_grad_finish(g.m_x2, (int)(c.ny / l.w_x2), g.m_y2, (int)(c.nx / l.w_y2), g.m_y1, g.m_x1, c.nx,
+                               c.ny, c.dt_fs / h->u.hbar, dldv_dev, h->stream));
+    HIP_TRY(hipMemcpyAsync(dL_dV, dldv_dev, h->nxy * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    // dL/dB: both x axes, Parseval factor 1/nx, factor 2 of 2 Im(conj(lambda) psi)
+    HIP_TRY(launch_reduce_parts(g.gb_x1, (int)(l.nb_x1 + l.nb_x2), 1, h->red_out, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->host_out, h->red_out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    *dL_dB = h->host_out[0] * 2.0 / c.nx;
+    *loss = L;
+    h->step -= h->rec_steps;
+    h->rec = false;
+    return HOM4D_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -756,6 +845,12 @@ int hom4d_create(const hom4d_cfg* cfg, void* hip_stream, hom4d** out) {
         return cleanup(HOM4D_EHIP);
     }
     if ((rc = build_twiddles(h)) || (rc = build_kinetic(h)) || (rc = build_coulomb(h))) return cleanup(rc);
+    // the fixed scratch of hom4d_grad_backward_noalloc: its address on this device, once
+    e = init_scratch(h->device);
+    if (e != hipSuccess) {
+        fail(HOM4D_EHIP, "device scratch address: %s", hipGetErrorString(e));
+        return cleanup(HOM4D_EHIP);
+    }
     h->plane_built = plane_available(nx, ny, h->mixed);
     *out = h;
     return HOM4D_OK;
@@ -1126,66 +1221,31 @@ int hom4d_grad_end(hom4d* h) {
 
 int hom4d_grad_backward(hom4d* h, const double* w_top, const double* coeffs, void* d_lambda, double* loss,
                         double* dL_dV, double* dL_dB) {
-    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
-    if (!coeffs || !d_lambda || !loss || !dL_dV || !dL_dB) return fail(HOM4D_EINVAL, "NULL argument");
-    if (((uintptr_t)d_lambda) % 16 != 0) return fail(HOM4D_EINVAL, "adjoint buffer must be 16-byte aligned");
-    int rc = check_weights(w_top, h->nxy);
+    int rc = grad_checks(h, w_top, coeffs, d_lambda, loss, dL_dV, dL_dB);
     if (rc) return rc;
-    if (!h->rec) return fail(HOM4D_ESTATE, "no recorded forward run (hom4d_grad_begin + hom4d_step)");
-    if (!h->psi) return fail(HOM4D_EUNBOUND, "no state bound");
-    if ((size_t)(h->rec_steps / h->ckpt_every + 1) * h->state_bytes > h->pool_bytes)
-        return fail(HOM4D_ESTATE, "recorded checkpoints exceed the pool (%zu bytes)", h->pool_bytes);
-    const hom4d_cfg& c = h->cfg;
-    const AxisPlan px1 = plan_axis(AX_X1, c.nx, c.ny, 2, true, h->mixed);
-    const AxisPlan px2 = plan_axis(AX_X2, c.nx, c.ny, 2, true, h->mixed);
-    const AxisPlan py1 = plan_axis(AX_Y1, c.nx, c.ny, 2, true, h->mixed);
-    const AxisPlan py2 = plan_axis(AX_Y2, c.nx, c.ny, 2, true, h->mixed);
-    const int64_t nb_x1 = px1.nlines / px1.W, nb_x2 = px2.nlines / px2.W, nb_y2 = py2.nlines / py2.W;
-    const int64_t len_m_x1 = px1.nlines, len_m_y1 = py1.nlines;
-    const size_t need = (size_t)(nb_x1 + nb_x2 + len_m_x1 + len_m_y1 + nb_x2 + nb_y2 + h->nxy);
+    const size_t need = grad_scratch_len(h);
     if (need > h->g_len) {
         if (h->g_buf) HIP_TRY(hipFree(h->g_buf));
         h->g_buf = nullptr;
+        h->g_len = 0;
         HIP_TRY(hipMalloc((void**)&h->g_buf, need * sizeof(double)));
         h->g_len = need;
     }
-    GradCtx g;
-    g.gb_x1 = h->g_buf;
-    g.gb_x2 = g.gb_x1 + nb_x1;
-    g.m_x1 = g.gb_x2 + nb_x2;
-    g.m_y1 = g.m_x1 + len_m_x1;
-    g.m_x2 = g.m_y1 + len_m_y1;
-    g.m_y2 = g.m_x2 + nb_x2;
-    double* dldv_dev = g.m_y2 + nb_y2;
-    HIP_TRY(launch_zero(h->g_buf, (int64_t)need, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->w_dev, w_top, h->nxy * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(launch_loss_lambda(h->psi, d_lambda, h->mixed, h->w_dev, coeffs, h->nxy, h->red_part, h->red_blocks,
-                               h->stream));
-    double L = 0.0;
-    if ((rc = fetch_reduction(h, 1, &L))) return rc;
-    // reverse sweep, segment by segment, restoring the state at every checkpoint
-    int64_t seg_end = h->rec_steps;
-    for (int64_t k = h->rec_steps / h->ckpt_every; k >= 0; --k) {
-        const int64_t seg_start = k * h->ckpt_every;
-        if (seg_end > seg_start) {
-            if ((rc = run_steps(h, seg_end - seg_start, 2, d_lambda, true, &g))) return rc;
-        }
-        HIP_TRY(hipMemcpyAsync(h->psi, h->pool + (size_t)k * h->state_bytes, h->state_bytes, hipMemcpyDeviceToDevice,
-                               h->stream));
-        seg_end = seg_start;
-    }
-    HIP_TRY(launch_grad_finish(g.m_x2, (int)(c.ny / px2.W), g.m_y2, (int)(c.nx / py2.W), g.m_y1, g.m_x1, c.nx, c.ny,
-                               c.dt_fs / h->u.hbar, dldv_dev, h->stream));
-    HIP_TRY(hipMemcpyAsync(dL_dV, dldv_dev, h->nxy * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    // dL/dB: both x axes, Parseval factor 1/nx, factor 2 of 2 Im(conj(lambda) psi)
-    HIP_TRY(launch_reduce_parts(g.gb_x1, (int)(nb_x1 + nb_x2), 1, h->red_out, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->host_out, h->red_out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    *dL_dB = h->host_out[0] * 2.0 / c.nx;
-    *loss = L;
-    h->step -= h->rec_steps;
-    h->rec = false;
-    return HOM4D_OK;
+    return grad_sweep(h, w_top, coeffs, d_lambda, loss, dL_dV, dL_dB, h->g_buf);
+}
+
+int hom4d_grad_backward_noalloc(hom4d* h, const double* w_top, const double* coeffs, void* d_lambda,
+                                double* loss, double* dL_dV, double* dL_dB) {
+    int rc = grad_checks(h, w_top, coeffs, d_lambda, loss, dL_dV, dL_dB);
+    if (rc) return rc;
+    if (h->timing) return fail(HOM4D_ESTATE, "pass timing is on (its event pool is created on demand)");
+    const size_t need = grad_scratch_len(h);
+    if (need > kScratchDoubles)
+        return fail(HOM4D_ENOMEM, "gradient partials need %zu doubles, the fixed scratch holds %zu", need,
+                    kScratchDoubles);
+    double* buf = scratch_on(h->device);
+    if (!buf) return fail(HOM4D_EHIP, "device scratch of device %d not initialised", h->device);
+    return grad_sweep(h, w_top, coeffs, d_lambda, loss, dL_dV, dL_dB, buf);
 }
 
 int hom4d_pass_timing(hom4d* h, int32_t enable) {

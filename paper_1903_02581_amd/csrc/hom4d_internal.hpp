@@ -124,4 +124,13 @@ hipError_t launch_grad_finish(const double* m_x2, int bpr_x2, const double* m_y2
                               double* dldv, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 
+// Fixed device scratch of the no-allocation reverse sweep: kScratchDoubles
+// FP64 values (64 MiB) per GPU.  init_scratch(device), with that device
+// current, takes the array's address on it once; scratch_on(device) returns
+// it afterwards (nullptr before).
+constexpr size_t kScratchDoubles = (size_t(64) << 20) / sizeof(double);
+constexpr int kMaxDevices = 64;
+hipError_t init_scratch(int device);
+double* scratch_on(int device);
+
 }  // namespace hom4d_impl

@@ -416,6 +416,37 @@ hipError_t launch_zero(double* p, int64_t count, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Gradient partials of the reverse sweep for callers that cannot allocate
+// (hom4d_grad_backward_noalloc): a fixed array in device memory, one copy per
+// GPU that loads the library.  Host code never names it: each device's address
+// is taken once, with that device current, and kept in scratch_ptrs.
+namespace {
+static __device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex scratch_mu;
+double* scratch_ptrs[kMaxDevices] = {};
+}  // namespace
+
+hipError_t init_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_ptrs[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptrs[device] = static_cast<double*>(ptr);
+    return hipSuccess;
+}
+
+double* scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    return scratch_ptrs[device];
+}
+
 hipError_t launch_grad_finish(const double* m_x2, int bpr_x2, const double* m_y2, int bpr_y2, const double* m_y1,
                               const double* m_x1, int nx, int ny, double gscale, double* dldv, hipStream_t s) {
     const int nxy = nx * ny;

@@ -32,7 +32,7 @@ EXPORTS = ["hom4d_create", "hom4d_destroy", "hom4d_validate_cfg", "hom4d_state_b
            "hom4d_save_checkpoint", "hom4d_load_checkpoint", "hom4d_step", "hom4d_observables",
            "hom4d_set_norm_tol", "hom4d_entanglement", "hom4d_gather_slice", "hom4d_marginal",
            "hom4d_conditional", "hom4d_grad_begin",
-           "hom4d_grad_backward", "hom4d_grad_end", "hom4d_run_pass", "hom4d_set_pass_plan",
+           "hom4d_grad_backward", "hom4d_grad_backward_noalloc", "hom4d_grad_end", "hom4d_run_pass", "hom4d_set_pass_plan",
            "hom4d_pass_plan", "hom4d_pass_timing", "hom4d_pass_times", "hom4d_strerror",
            "hom4d_last_error"]
 
@@ -93,6 +93,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "hom4d_conditional": ([vp, c_int32, c_int32, dp], c_int),
         "hom4d_grad_begin": ([vp, c_int32, vp, c_size_t], c_int),
         "hom4d_grad_backward": ([vp, dp, dp, vp, dp, dp, dp], c_int),
+        "hom4d_grad_backward_noalloc": ([vp, dp, dp, vp, dp, dp, dp], c_int),
         "hom4d_grad_end": ([vp], c_int),
         "hom4d_run_pass": ([vp, c_int32, c_int32], c_int),
         "hom4d_set_pass_plan": ([vp, c_int32], c_int),
@@ -296,8 +297,9 @@ class Propagator:
         self._check(self.lib.hom4d_grad_begin(self.h, int(ckpt_every),
                                               c_void_p(self._pool.data_ptr()), nb), "grad_begin")
 
-    def grad_backward(self, w_top, coeffs=(1.0, 0.0, 0.0, 1.0)):
-        """Reverse sweep: returns (L, dL/dV [nx, ny], dL/dB)."""
+    def grad_backward(self, w_top, coeffs=(1.0, 0.0, 0.0, 1.0), noalloc: bool = False):
+        """Reverse sweep: returns (L, dL/dV [nx, ny], dL/dB).  noalloc: through
+        hom4d_grad_backward_noalloc (fixed device scratch, no allocation in the call)."""
         import torch
         w = np.ascontiguousarray(np.asarray(w_top, dtype=np.float64)).reshape(self.nx, self.ny)
         cf = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
@@ -306,9 +308,10 @@ class Propagator:
         loss = c_double()
         dldb = c_double()
         dldv = np.empty((self.nx, self.ny), dtype=np.float64)
-        self._check(self.lib.hom4d_grad_backward(self.h, _dptr(w), _dptr(cf),
-                                                 c_void_p(self._lam.data_ptr()), byref(loss),
-                                                 _dptr(dldv), byref(dldb)), "grad_backward")
+        fn = self.lib.hom4d_grad_backward_noalloc if noalloc else self.lib.hom4d_grad_backward
+        self._check(fn(self.h, _dptr(w), _dptr(cf), c_void_p(self._lam.data_ptr()), byref(loss),
+                       _dptr(dldv), byref(dldb)),
+                    "grad_backward_noalloc" if noalloc else "grad_backward")
         return float(loss.value), dldv, float(dldb.value)
 
     def set_pass_plan(self, plan: int):
