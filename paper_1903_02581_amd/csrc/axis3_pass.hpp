@@ -67,7 +67,10 @@ __device__ __forceinline__ void lds_barrier() {
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT, bool PERS>
+// WC > 0: the block holds WC lines, a compile-time constant (the nominal width
+// of the pass, axis3_nominal_w), so every LDS address is a per-thread base plus
+// an immediate offset; WC = 0: a.W lines, for grids that allow fewer.
+template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT, bool PERS, int WC>
 __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !std::is_same<S, double2>::value)) k_axis3(const PassArgs a) {
     static_assert(!PERS || NST == 1, "only the forward passes are persistent");
     using NW = Net3<R1, R2, R3, T>;
@@ -75,7 +78,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
     using X = Xchg<S>;
     extern __shared__ double2 lds_raw[];
 
-    const int W = a.W;
+    const int W = WC > 0 ? WC : a.W;
     const int tid = threadIdx.x;
     int t, cl;
     if constexpr (AXIS == AX_Y2) {
@@ -114,8 +117,20 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             line_sync<AXIS, T>();
     };
     // element jj * R1 + n1 of a thread: line position n1 N2 + t + T jj
-    auto elem_off = [&](const LineGeom<AXIS>& lg, int jj, int n1) -> int64_t {
-        return (int64_t)(n1 * N2 + t + T * jj) * lg.sN;
+    // visit the thread's elements e = jj R1 + n1 of a line (line position
+    // n1 N2 + t + T jj) with their addresses, stepping from one to the next by a
+    // 64-bit add rather than forming each offset by multiplication
+    auto walk = [&](const LineGeom<AXIS>& lg, auto* base, auto&& fn) {
+        const int64_t step = (int64_t)N2 * lg.sN;
+#pragma unroll
+        for (int jj = 0; jj < JA; ++jj) {
+            auto* p = base + (int64_t)(t + T * jj) * lg.sN;
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) {
+                fn(jj * R1 + n1, p);
+                p += step;
+            }
+        }
     };
 
     // Transform round trip of the block's tile held in v (loaded elements in,
@@ -293,12 +308,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         }
 
 #pragma unroll
-        for (int s = 0; s < NST; ++s)
-#pragma unroll
-            for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1)
-                    st<S, NT>(ps[s] + elem_off(lg, jj, n1), v[s][jj * R1 + n1]);
+        for (int s = 0; s < NST; ++s) walk(lg, ps[s], [&](int e, S* p) { st<S, NT>(p, v[s][e]); });
 
         if constexpr (NST == 2) {
             // the same partial-sum layout as the two-stage pass: dL/dB per block; the
@@ -335,11 +345,8 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         uint32_t tile = blockIdx.x;
         if (tile < ntiles) {
             const LineGeom<AXIS> lg(a, tile * (uint32_t)W + (uint32_t)cl);
-            const S* p = reinterpret_cast<const S*>(a.psi) + lg.base;
-#pragma unroll
-            for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1) raw[jj * R1 + n1] = ld_raw<S, NT>(p + elem_off(lg, jj, n1));
+            walk(lg, reinterpret_cast<const S*>(a.psi) + lg.base,
+                 [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
         }
         for (; tile < ntiles; tile += gridDim.x) {
             // the thread's line slot and position index pass through an empty asm
@@ -355,11 +362,8 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             const uint32_t next = tile + gridDim.x;
             if (next < ntiles) {
                 const LineGeom<AXIS> ln(a, next * (uint32_t)W + (uint32_t)cl);
-                const S* p = reinterpret_cast<const S*>(a.psi) + ln.base;
-#pragma unroll
-                for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-                    for (int n1 = 0; n1 < R1; ++n1) raw[jj * R1 + n1] = ld_raw<S, NT>(p + elem_off(ln, jj, n1));
+                walk(ln, reinterpret_cast<const S*>(a.psi) + ln.base,
+                     [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
             }
             round_trip(lg, line, ps);
         }
@@ -372,11 +376,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         if constexpr (NST == 2) ps[1] = reinterpret_cast<S*>(a.lam) + lg.base;
         S raw[NST][E];
 #pragma unroll
-        for (int s = 0; s < NST; ++s)
-#pragma unroll
-            for (int jj = 0; jj < JA; ++jj)
-#pragma unroll
-                for (int n1 = 0; n1 < R1; ++n1) raw[s][jj * R1 + n1] = ld_raw<S, NT>(ps[s] + elem_off(lg, jj, n1));
+        for (int s = 0; s < NST; ++s) walk(lg, ps[s], [&](int e, S* p) { raw[s][e] = ld_raw<S, NT>(p); });
         after_loads();
 #pragma unroll
         for (int s = 0; s < NST; ++s)
@@ -387,12 +387,20 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
 }
 
 // Three-stage factorisations: n = R1 R2 R3 on T threads per line.
+// The compile-time-width form when the block takes the pass's nominal width w.
+template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT, bool PERS>
+AxisKernel pick_w(int w) {
+    constexpr int WN = axis3_nominal_w(AXIS, R1 * R2 * R3, T, NST, !std::is_same<S, double2>::value);
+    return w == WN ? k_axis3<S, AXIS, R1, R2, R3, T, NST, VK, NT, PERS, WN>
+                   : k_axis3<S, AXIS, R1, R2, R3, T, NST, VK, NT, PERS, 0>;
+}
+
 template <class S, int AXIS, int NST, int VK, bool NT, bool PERS = false>
-AxisKernel pick3(int n, int* t) {
+AxisKernel pick3(int n, int w, int* t) {
     switch (n) {
-        case 96: *t = 8; return k_axis3<S, AXIS, 12, 4, 2, 8, NST, VK, NT, PERS>;
-        case 128: *t = 16; return k_axis3<S, AXIS, 8, 4, 4, 16, NST, VK, NT, PERS>;
-        case 256: *t = 32; return k_axis3<S, AXIS, 8, 8, 4, 32, NST, VK, NT, PERS>;
+        case 96: *t = 8; return pick_w<S, AXIS, 12, 4, 2, 8, NST, VK, NT, PERS>(w);
+        case 128: *t = 16; return pick_w<S, AXIS, 8, 4, 4, 16, NST, VK, NT, PERS>(w);
+        case 256: *t = 32; return pick_w<S, AXIS, 8, 8, 4, 32, NST, VK, NT, PERS>(w);
         default: *t = 0; return nullptr;
     }
 }
@@ -402,28 +410,28 @@ AxisKernel pick3(int n, int* t) {
 // x passes carry none, y1 (before its transform) and y2 (after) carry it.
 // Persistent forms: the x1 and y1 passes without a potential factor.
 template <class S, bool NT>
-AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, bool pers, int* t) {
+AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, bool pers, int w, int* t) {
     if (pers) {
-        if (nst == 1 && vk == 0 && axis == AX_X1) return pick3<S, AX_X1, 1, 0, NT, true>(n, t);
-        if (nst == 1 && vk == 0 && axis == AX_Y1) return pick3<S, AX_Y1, 1, 0, NT, true>(n, t);
+        if (nst == 1 && vk == 0 && axis == AX_X1) return pick3<S, AX_X1, 1, 0, NT, true>(n, w, t);
+        if (nst == 1 && vk == 0 && axis == AX_Y1) return pick3<S, AX_Y1, 1, 0, NT, true>(n, w, t);
         *t = 0;
         return nullptr;
     }
     if (nst == 2) {
         switch (axis) {
             case AX_X1:
-                if (vk == 0) return pick3<S, AX_X1, 2, 0, NT>(n, t);
+                if (vk == 0) return pick3<S, AX_X1, 2, 0, NT>(n, w, t);
                 break;
             case AX_X2:
-                if (vk == 0) return pick3<S, AX_X2, 2, 0, NT>(n, t);
+                if (vk == 0) return pick3<S, AX_X2, 2, 0, NT>(n, w, t);
                 break;
             case AX_Y1:
-                if (vk == 1) return pick3<S, AX_Y1, 2, 1, NT>(n, t);
-                if (vk == 2) return pick3<S, AX_Y1, 2, 2, NT>(n, t);
+                if (vk == 1) return pick3<S, AX_Y1, 2, 1, NT>(n, w, t);
+                if (vk == 2) return pick3<S, AX_Y1, 2, 2, NT>(n, w, t);
                 break;
             case AX_Y2:
-                if (vk == 1) return pick3<S, AX_Y2, 2, 1, NT>(n, t);
-                if (vk == 2) return pick3<S, AX_Y2, 2, 2, NT>(n, t);
+                if (vk == 1) return pick3<S, AX_Y2, 2, 1, NT>(n, w, t);
+                if (vk == 2) return pick3<S, AX_Y2, 2, 2, NT>(n, w, t);
                 break;
             default: break;
         }
@@ -432,21 +440,21 @@ AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, bool pers, int* t) {
     }
     switch (axis) {
         case AX_X1:
-            if (vk == 0) return pick3<S, AX_X1, 1, 0, NT>(n, t);
+            if (vk == 0) return pick3<S, AX_X1, 1, 0, NT>(n, w, t);
             break;
         case AX_X2:
-            if (vk == 0) return pick3<S, AX_X2, 1, 0, NT>(n, t);
-            if (vk == 1) return pick3<S, AX_X2, 1, 1, NT>(n, t);
-            if (vk == 2) return pick3<S, AX_X2, 1, 2, NT>(n, t);
+            if (vk == 0) return pick3<S, AX_X2, 1, 0, NT>(n, w, t);
+            if (vk == 1) return pick3<S, AX_X2, 1, 1, NT>(n, w, t);
+            if (vk == 2) return pick3<S, AX_X2, 1, 2, NT>(n, w, t);
             break;
         case AX_Y1:
-            if (vk == 0) return pick3<S, AX_Y1, 1, 0, NT>(n, t);
-            if (vk == 1) return pick3<S, AX_Y1, 1, 1, NT>(n, t);
-            if (vk == 2) return pick3<S, AX_Y1, 1, 2, NT>(n, t);
+            if (vk == 0) return pick3<S, AX_Y1, 1, 0, NT>(n, w, t);
+            if (vk == 1) return pick3<S, AX_Y1, 1, 1, NT>(n, w, t);
+            if (vk == 2) return pick3<S, AX_Y1, 1, 2, NT>(n, w, t);
             break;
         case AX_Y2:
-            if (vk == 1) return pick3<S, AX_Y2, 1, 1, NT>(n, t);
-            if (vk == 2) return pick3<S, AX_Y2, 1, 2, NT>(n, t);
+            if (vk == 1) return pick3<S, AX_Y2, 1, 1, NT>(n, w, t);
+            if (vk == 2) return pick3<S, AX_Y2, 1, 2, NT>(n, w, t);
             break;
         default: break;
     }
@@ -455,8 +463,8 @@ AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, bool pers, int* t) {
 }
 
 template <class S>
-AxisKernel pick_axis3(int axis, int n, int vk, int nst, bool nt, bool pers, int* t) {
-    return nt ? pick_axis3_nt<S, true>(axis, n, vk, nst, pers, t) : pick_axis3_nt<S, false>(axis, n, vk, nst, pers, t);
+AxisKernel pick_axis3(int axis, int n, int vk, int nst, bool nt, bool pers, int w, int* t) {
+    return nt ? pick_axis3_nt<S, true>(axis, n, vk, nst, pers, w, t) : pick_axis3_nt<S, false>(axis, n, vk, nst, pers, w, t);
 }
 
 }  // namespace dev

@@ -140,17 +140,10 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         // dual-state blocks take two exchange areas within 80 KB, counted in
         // the storage's entry size.
         p.t = t3;
-        const bool wide = p.n != 128;
-        const int bt = axis3_block_threads(axis, p.n, nst, mixed);
         // The complex64 x2 pass at n = 128 takes 32 lines as well (512 threads,
         // complex64 entries within 80 KB): x2+V 842 -> 812 us at 128 x 96, 317 ->
         // 310 us at 128 x 64 (the x1 pass measured slower that way, 581 -> 647).
-        const bool x2_32 = p.n == 128 && nst == 1 && mixed && axis == AX_X2;
-        int64_t w = (bt == 1024 ? 1024 : (wide || x2_32) ? 512 : 256) / t3;
-        const int64_t cap = (bt == 1024 || x2_32) ? (81920 - 2 * p.n * 16) / ((int64_t)p.n * 8) - 1
-                          : nst == 1 ? ((wide ? 81920 : 49152) - 2 * p.n * 16) / ((int64_t)p.n * 16) - 1
-                                     : (81920 - 2 * p.n * 16) / ((int64_t)2 * p.n * (mixed ? 8 : 16)) - 1;
-        while (w > cap) w >>= 1;
+        int64_t w = axis3_nominal_w(axis, p.n, t3, nst, mixed);
         w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
         if (axis == AX_X2) w = std::min<int64_t>(w, ilog2_pow2_divisor(ny));
         if (axis == AX_Y2 && grad) w = std::min<int64_t>(w, ilog2_pow2_divisor(nx));

@@ -69,6 +69,27 @@ __host__ __device__ constexpr int axis3_block_threads(int axis, int n, int nst, 
     return (n == 256 && nst == 1 && mixed && axis == AX_X1) ? 1024 : 512;
 }
 
+// Lines per block of the three-stage kernel before the grid's divisibility
+// limits (plan_axis may halve it further): the block's threads over the
+// threads per line, halved until the exchange area and the staged factors fit
+// the LDS budget -- 48 KB for the one-state n = 128 passes (three or more
+// blocks per CU), 80 KB otherwise, counted in complex128 entries for the
+// one-state passes of 256- or 512-thread blocks and in the storage's entry
+// size for the 1024-thread and 32-line n = 128 complex64 blocks and the
+// two-state passes.  The kernel is built with this width as a compile-time
+// constant (LDS offsets become immediates) and with a run-time width.
+__host__ __device__ constexpr int axis3_nominal_w(int axis, int n, int t3, int nst, bool mixed) {
+    const int bt = axis3_block_threads(axis, n, nst, mixed);
+    const bool wide = n != 128;
+    const bool x2_32 = n == 128 && nst == 1 && mixed && axis == AX_X2;
+    int w = (bt == 1024 ? 1024 : (wide || x2_32) ? 512 : 256) / t3;
+    const int cap = (bt == 1024 || x2_32) ? (81920 - 2 * n * 16) / (n * 8) - 1
+                  : nst == 1 ? ((wide ? 81920 : 49152) - 2 * n * 16) / (n * 16) - 1
+                             : (81920 - 2 * n * 16) / (2 * n * (mixed ? 8 : 16)) - 1;
+    while (w > cap) w >>= 1;
+    return w;
+}
+
 // Whether the two-stage kernel's exchanges on this axis are complex64 (with
 // complex64 storage: every axis but x1).
 __host__ __device__ constexpr bool axis_xchg_c64(int axis, bool mixed) { return mixed && axis != AX_X1; }

@@ -38,8 +38,8 @@ AxisKernel pick_axis_f64_1(int axis, int n, int vk, bool nt, int* t);
 AxisKernel pick_axis_f64_2(int axis, int n, int vk, bool nt, int* t);
 AxisKernel pick_axis_f32_1(int axis, int n, int vk, bool nt, int* t);
 AxisKernel pick_axis_f32_2(int axis, int n, int vk, bool nt, int* t);
-AxisKernel pick_axis3_f64(int axis, int n, int vk, int nst, bool nt, bool pers, int* t);
-AxisKernel pick_axis3_f32(int axis, int n, int vk, int nst, bool nt, bool pers, int* t);
+AxisKernel pick_axis3_f64(int axis, int n, int vk, int nst, bool nt, bool pers, int w, int* t);
+AxisKernel pick_axis3_f32(int axis, int n, int vk, int nst, bool nt, bool pers, int w, int* t);
 AxisKernel pick_plane_f64(int nx, int ny, int vk, int* nt);
 AxisKernel pick_plane_f32(int nx, int ny, int vk, int* nt);
 
@@ -269,7 +269,8 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, bool pers, const Pa
     const int vk = a.vmode == 0 ? 0 : (a.vdirect ? 2 : 1);
     const bool nt = a.nt != 0;
     if (axis3_threads(n, nst) > 0)
-        fn = mixed ? pick_axis3_f32(axis, n, vk, nst, nt, pers, &t) : pick_axis3_f64(axis, n, vk, nst, nt, pers, &t);
+        fn = mixed ? pick_axis3_f32(axis, n, vk, nst, nt, pers, a.W, &t)
+                   : pick_axis3_f64(axis, n, vk, nst, nt, pers, a.W, &t);
     else if (pers)
         return hipErrorInvalidValue;  // only the three-stage passes have a persistent form
     else if (!mixed)
