@@ -43,9 +43,12 @@ class BunchingLoss(torch.autograd.Function):
         prop.init_state(psi_a, psi_b, sym)
         prop.grad_begin(ckpt_every, steps)
         prop.step(steps)
+        # the four region probabilities are the library's FP64 reduction of the final
+        # state; the reverse sweep recomputes L with the same weights (checked in backward)
         o = prop.observables(w_top)
         c = np.asarray(coeffs, dtype=np.float64)
         loss = c[0] * o["p_tt"] + c[1] * o["p_tb"] + c[2] * o["p_bt"] + c[3] * o["p_bb"]
+        ctx.loss = loss
         ctx.prop = prop
         ctx.w_top = w_top
         ctx.coeffs = c
@@ -56,7 +59,9 @@ class BunchingLoss(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_out):
-        _, dldv, dldb = ctx.prop.grad_backward(ctx.w_top, ctx.coeffs)
+        loss, dldv, dldb = ctx.prop.grad_backward(ctx.w_top, ctx.coeffs)
+        if not abs(loss - ctx.loss) <= 1e-12 * max(1.0, abs(ctx.loss)):
+            raise RuntimeError(f"reverse sweep's loss {loss!r} differs from the forward's {ctx.loss!r}")
         g = grad_out.detach().cpu().double()
         gv = torch.from_numpy(dldv).to(ctx.v_device, ctx.v_dtype) * g.to(ctx.v_device)
         gb = torch.tensor(dldb, dtype=torch.float64) * g
