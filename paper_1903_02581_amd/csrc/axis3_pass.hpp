@@ -73,6 +73,8 @@ __device__ __forceinline__ void lds_barrier() {
 template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT, bool PERS, int WC>
 __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !std::is_same<S, double2>::value)) k_axis3(const PassArgs a) {
     static_assert(!PERS || NST == 1, "only the forward passes are persistent");
+    // the reverse sweep (two states) applies every factor conjugated
+    constexpr bool CONJ = NST == 2;
     using NW = Net3<R1, R2, R3, T>;
     constexpr int N = NW::N, N2 = NW::N2, JA = NW::JA, G1 = NW::G1, G2 = NW::G2, E = NW::E;
     using X = Xchg<S>;
@@ -101,7 +103,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             w = a.tw[i];
         } else {
             w = a.ktab[i - N];
-            if (a.kconj) w = conjd(w);
+            if constexpr (CONJ) w = conjd(w);
         }
         twl[i] = w;
     }
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 const double2 f0 = tb.fixed();
                 batched<E, 4>([&](int e) { return tb.load((e % R1) * N2 + T * (e / R1)); },
                               [&](int e, const VLoad& l) {
-                                  const double2 f = tb.combine(f0, l, a.kconj);
+                                  const double2 f = tb.template combine<CONJ>(f0, l);
 #pragma unroll
                                   for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
                               });
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                     [&](int e, const VLoad& l) {
                         int c[4];
                         coords(e, c);
-                        const double2 f = vcombine<VKF>(a, l, c[0], c[1], c[2], c[3]);
+                        const double2 f = vcombine<VKF, CONJ>(a, l, c[0], c[1], c[2], c[3]);
 #pragma unroll
                         for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
                     });
@@ -255,7 +257,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                     f = twl[N + k];
                 } else {
                     f = kf[k3];
-                    if (a.kconj) f = conjd(f);
+                    if constexpr (CONJ) f = conjd(f);
                 }
 #pragma unroll
                 for (int s = 0; s < NST; ++s) v[s][ii * R3 + k3] = cmul(v[s][ii * R3 + k3], f);

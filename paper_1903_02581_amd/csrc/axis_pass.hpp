@@ -154,7 +154,7 @@ __device__ __forceinline__ VLoad vload(const PassArgs& a, int i1, int j1, int i2
     if constexpr (VK == 1 || VK == 3) {
         l.q = a.a1[i2 * a.ny + j2];
         if constexpr (VK == 1) l.p = a.a1[i1 * a.ny + j1];
-        if (a.ac) l.r = a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)];
+        l.r = a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)];
     } else {
         l.p = make_double2(a.vtab[i1 * a.ny + j1], a.vtab[i2 * a.ny + j2]);
     }
@@ -165,14 +165,14 @@ __device__ __forceinline__ VLoad vload(const PassArgs& a, int i1, int j1, int i2
 // loaded entries.  VK = 1: product of the one-body and two-body factor tables;
 // VK = 2: the FP64 angle evaluated here, reduced mod 2 pi, then sincos; VK = 3:
 // as VK = 1 without the one-body factor of electron 1 (applied by the caller).
-template <int VK>
+template <int VK, bool CONJ>
 __device__ __forceinline__ double2 vcombine(const PassArgs& a, const VLoad& l, int i1, int j1, int i2, int j2) {
     double2 f;
     if constexpr (VK == 1 || VK == 3) {
         f = l.q;
         if constexpr (VK == 1) f = cmul(l.p, f);
-        if (a.ac) f = cmul(f, l.r);
-        if (a.kconj) f = conjd(f);
+        f = cmul(f, l.r);
+        if constexpr (CONJ) f = conjd(f);
     } else {
         double v = l.p.x + l.p.y;
         if (a.ck != 0.0) {
@@ -194,18 +194,18 @@ __device__ __forceinline__ double2 vcombine(const PassArgs& a, const VLoad& l, i
 // The same factor with its table entries loaded in place (the fused plane pass
 // applies it element by element inside its LDS stages; there the batched form
 // measured slower: 64x64 FP64 plane pass 104 -> 130 VGPRs, 127 -> 163 us).
-template <int VK>
+template <int VK, bool CONJ>
 __device__ __forceinline__ double2 vfactor(const PassArgs& a, int i1, int j1, int i2, int j2) {
     double2 f;
     if constexpr (VK == 1 || VK == 3) {
         f = a.a1[i2 * a.ny + j2];
         if constexpr (VK == 1) f = cmul(a.a1[i1 * a.ny + j1], f);
-        if (a.ac) f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)]);
-        if (a.kconj) f = conjd(f);
+        f = cmul(f, a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (j1 - j2 + a.ny - 1)]);
+        if constexpr (CONJ) f = conjd(f);
     } else {
         VLoad l;
         l.p = make_double2(a.vtab[i1 * a.ny + j1], a.vtab[i2 * a.ny + j2]);
-        f = vcombine<VK>(a, l, i1, j1, i2, j2);
+        f = vcombine<VK, CONJ>(a, l, i1, j1, i2, j2);
     }
     return f;
 }
@@ -274,29 +274,31 @@ struct LineGeom {
     __device__ __forceinline__ LineGeom(const PassArgs& a, uint32_t line) {
         const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny, nxy = nx * ny;
         if constexpr (AXIS == AX_X1) {
-            j1 = (int)(line / nxy);
-            i2 = (int)((line / ny) % nx);
-            j2 = (int)(line % ny);
+            const uint32_t o = a.dny.div(line);
+            j1 = (int)a.dnx.div(o);
+            i2 = (int)a.dnx.mod(o, (uint32_t)j1);
+            j2 = (int)a.dny.mod(line, o);
             base = line;
             sN = (int64_t)ny * nxy;
         } else if constexpr (AXIS == AX_Y1) {
-            i1 = (int)(line / nxy);
-            const uint32_t c = line % nxy;
-            i2 = (int)(c / ny);
-            j2 = (int)(c % ny);
+            i1 = (int)a.dnxy.div(line);
+            const uint32_t c = a.dnxy.mod(line, (uint32_t)i1);
+            i2 = (int)a.dny.div(c);
+            j2 = (int)a.dny.mod(c, (uint32_t)i2);
             base = (int64_t)i1 * ny * nxy + c;
             sN = nxy;
         } else if constexpr (AXIS == AX_X2) {
-            const uint32_t o = line / ny;
-            i1 = (int)(o / ny);
-            j1 = (int)(o % ny);
-            j2 = (int)(line % ny);
+            const uint32_t o = a.dny.div(line);
+            i1 = (int)a.dny.div(o);
+            j1 = (int)a.dny.mod(o, (uint32_t)i1);
+            j2 = (int)a.dny.mod(line, o);
             base = (int64_t)o * nxy + j2;
             sN = ny;
         } else {
-            i1 = (int)(line / nxy);
-            j1 = (int)((line / nx) % ny);
-            i2 = (int)(line % nx);
+            const uint32_t o = a.dnx.div(line);
+            i1 = (int)a.dny.div(o);
+            j1 = (int)a.dny.mod(o, (uint32_t)i1);
+            i2 = (int)a.dnx.mod(line, o);
             base = (int64_t)line * ny;
             sN = 1;
         }
@@ -311,6 +313,8 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     constexpr int JA = N2 / T;  // stage-A columns per thread
     constexpr int IB = N1 / T;  // stage-B rows per thread
     static_assert(N1 % T == 0 && N2 % T == 0, "t must divide both factors");
+    // the reverse sweep (two states) applies every factor conjugated
+    constexpr bool CONJ = NST == 2;
     // complex64 exchanges with complex64 storage, except on the x1 pass, which
     // measured slower with them (48x48: 27.7 -> 32.8 us)
     using X = Xchg<typename std::conditional<axis_xchg_c64(AXIS, true), S, double2>::type>;
@@ -352,7 +356,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
             v = a.tw[i];
         } else if (i < 2 * N) {
             v = a.ktab[i - N];
-            if (a.kconj) v = conjd(v);
+            if constexpr (CONJ) v = conjd(v);
         } else {
             v = a.a1[a1_row + i - 2 * N];
         }
@@ -369,14 +373,10 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
         if constexpr (A1_LDS) {
             const double2 f2 = a.a1[i2 * a.ny + j2];  // electron 2's factor: the same along the line
             batched<E, 8>(
-                [&](int e) {
-                    return a.ac ? a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (pos(e) - j2 + a.ny - 1)]
-                                : make_double2(1.0, 0.0);
-                },
+                [&](int e) { return a.ac[(i1 - i2 + a.nx - 1) * (2 * a.ny - 1) + (pos(e) - j2 + a.ny - 1)]; },
                 [&](int e, double2 fc) {
-                    double2 f = cmul(twl[2 * N + pos(e)], f2);
-                    if (a.ac) f = cmul(f, fc);
-                    if (a.kconj) f = conjd(f);
+                    double2 f = cmul(cmul(twl[2 * N + pos(e)], f2), fc);
+                    if constexpr (CONJ) f = conjd(f);
 #pragma unroll
                     for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
                 });
@@ -390,7 +390,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
                 [&](int e, const VLoad& l) {
                     int c[4];
                     elem_coord<AXIS>(i1, j1, i2, j2, pos(e), c);
-                    const double2 f = vcombine<VKF>(a, l, c[0], c[1], c[2], c[3]);
+                    const double2 f = vcombine<VKF, CONJ>(a, l, c[0], c[1], c[2], c[3]);
 #pragma unroll
                     for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
                 });
@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(256) k_axis(const PassArgs a) {
     } else {
         batched<E, 8>([&](int e) { return kt[wave_number(e) * kstride]; },
                       [&](int e, double2 f) {
-                          if (a.kconj) f = conjd(f);
+                          if constexpr (CONJ) f = conjd(f);
 #pragma unroll
                           for (int s = 0; s < NST; ++s) v[s][e] = cmul(v[s][e], f);
                       });
@@ -609,7 +609,7 @@ struct LineTables {
         const int64_t ny = a.ny, cy = 2 * (int64_t)a.ny - 1;
         p1 = a.a1 + (c[0] * ny + c[1]);
         p2 = a.a1 + (c[2] * ny + c[3]);
-        pc = a.ac ? a.ac + ((int64_t)(c[0] - c[2] + a.nx - 1) * cy + (c[1] - c[3] + a.ny - 1)) : nullptr;
+        pc = a.ac + ((int64_t)(c[0] - c[2] + a.nx - 1) * cy + (c[1] - c[3] + a.ny - 1));
         step = (AXIS == AX_X1 || AXIS == AX_X2) ? ny : 1;
         cstep = (AXIS == AX_X1) ? cy : (AXIS == AX_X2) ? -cy : (AXIS == AX_Y1) ? 1 : -1;
     }
@@ -623,17 +623,18 @@ struct LineTables {
     __device__ __forceinline__ VLoad load(int dm) const {
         VLoad l;
         l.q = (AXIS == AX_X1 || AXIS == AX_Y1) ? p1[dm * step] : p2[dm * step];
-        if (pc) l.r = pc[dm * cstep];
+        l.r = pc[dm * cstep];
         return l;
     }
-    __device__ __forceinline__ double2 combine(double2 f0, const VLoad& l, bool conj) const {
+    template <bool CONJ>
+    __device__ __forceinline__ double2 combine(double2 f0, const VLoad& l) const {
         double2 f;
         if constexpr (AXIS == AX_X1 || AXIS == AX_Y1)
             f = cmul(l.q, f0);
         else
             f = cmul(f0, l.q);
-        if (pc) f = cmul(f, l.r);
-        return conj ? conjd(f) : f;
+        f = cmul(f, l.r);
+        return CONJ ? conjd(f) : f;
     }
 };
 

@@ -377,6 +377,22 @@ int sync_check(hom4d* h, const char* what) {
     return HOM4D_OK;
 }
 
+// Div3 of d = 2^a 3^c, c <= 2, a >= 1 (validate() admits only such extents).
+Div3 make_div3(uint32_t d) {
+    uint32_t a = 0, c = 0, r = d;
+    while (r % 2 == 0) { r /= 2; ++a; }
+    while (r % 3 == 0) { r /= 3; ++c; }
+    Div3 q{};
+    q.d = d;
+    if (r != 1 || c > 2 || a < 1) return q;  // not reached for supported extents
+    if (c == 0) {
+        q.s1 = a - 1; q.m = 0x80000000u; q.s2 = 0;
+    } else {
+        q.s1 = a; q.m = c == 1 ? 0xAAAAAAABu : 0x38E38E39u; q.s2 = 1;
+    }
+    return q;
+}
+
 enum KTab { KX_HALF, KX_FULL, KY_FULL };
 
 struct GradCtx {
@@ -391,15 +407,19 @@ struct GradCtx {
 int run_pass(hom4d* h, int axis, KTab kt, int vmode, int nst, void* lam, bool reverse, int gflags,
              const GradCtx* g) {
     const hom4d_cfg& c = h->cfg;
+    // the pass kernels conjugate every factor exactly when they carry two states
+    if (reverse != (nst == 2)) return fail(HOM4D_EINVAL, "internal: a reverse pass carries the adjoint state");
     AxisPlan p = plan_axis(axis, c.nx, c.ny, nst, nst == 2, h->mixed);
     PassArgs a{};
     a.psi = h->psi;
     a.lam = lam;
     a.nx = c.nx;
     a.ny = c.ny;
+    a.dnx = make_div3((uint32_t)c.nx);
+    a.dny = make_div3((uint32_t)c.ny);
+    a.dnxy = make_div3((uint32_t)(c.nx * c.ny));
     a.W = p.W;
     a.ntiles = (uint32_t)(p.nlines / p.W);
-    a.kconj = reverse ? 1 : 0;
     a.tw = (axis == AX_X1 || axis == AX_X2) ? h->tw_x : h->tw_y;
     if (axis == AX_X2)
         a.ktab = kt == KX_HALF ? h->kxt_half : h->kxt_full;
@@ -417,7 +437,7 @@ int run_pass(hom4d* h, int axis, KTab kt, int vmode, int nst, void* lam, bool re
     // then hits what the previous one wrote.
     a.nt = (h->state_bytes > (size_t(1) << 30) || (axis == AX_X1 && h->state_bytes >= (size_t(1) << 29))) ? 1 : 0;
     a.a1 = h->a1_half;
-    a.ac = (c.coulomb_c != 0.0) ? h->ac_half : nullptr;
+    a.ac = h->ac_half;  // all (1, 0) without the Coulomb term: the product is then exact
     a.vdirect = c.coulomb_mode == HOM4D_COULOMB_DIRECT ? 1 : 0;
     a.vtab = h->v_dev;
     a.vscale = (reverse ? -0.5 : 0.5) * c.dt_fs / h->u.hbar;
@@ -457,7 +477,7 @@ int run_plane(hom4d* h, KTab kt) {
     a.tw2 = h->tw_y;
     a.ktab2 = h->ky_full;
     a.a1 = h->a1_half;
-    a.ac = (c.coulomb_c != 0.0) ? h->ac_half : nullptr;
+    a.ac = h->ac_half;  // all (1, 0) without the Coulomb term: the product is then exact
     a.vdirect = c.coulomb_mode == HOM4D_COULOMB_DIRECT ? 1 : 0;
     a.vtab = h->v_dev;
     a.vscale = 0.5 * c.dt_fs / h->u.hbar;

@@ -17,15 +17,26 @@ enum GradFlags : int {
     G_MOUT = 4,  // ... of the real-space states written back
 };
 
+// Division by a grid extent d = 2^a 3^c (c <= 2; every supported nx, ny and
+// nx ny has this form) without an integer divide: x / d = mulhi(x >> s1, m) >> s2,
+// where m = ceil(2^33 / 3^c) for c > 0 (0xAAAAAAAB for 3, 0x38E38E39 for 9:
+// m 3^c - 2^33 = 1, exact for every 32-bit dividend) with s2 = 1, and for c = 0
+// m = 2^31, s1 = a - 1, s2 = 0 (a plain shift by a, a >= 1).
+struct Div3 {
+    uint32_t s1, m, s2, d;
+    __device__ __forceinline__ uint32_t div(uint32_t x) const { return __umulhi(x >> s1, m) >> s2; }
+    __device__ __forceinline__ uint32_t mod(uint32_t x, uint32_t q) const { return x - q * d; }
+};
+
 // Everything one per-axis pass needs.  Axis lines have length n = nx (x axes)
 // or ny (y axes); the 4D state is row-major [x1][y1][x2][y2].
 struct PassArgs {
     void* psi;                // state, complex128 or complex64
     void* lam;                // adjoint state (dual-state passes only)
     int nx, ny;
+    Div3 dnx, dny, dnxy;      // division by nx, ny and nx ny (line numbers -> coordinates)
     int W;                    // lines per block
     uint32_t ntiles;          // tiles of W lines (nlines / W); a persistent pass's grid may be smaller
-    int kconj;                // use conj(ktab) and conj(potential factor): reverse sweep
     const double2* tw;        // twiddles exp(-2 pi i j / n), j < n
     const double2* ktab;      // k-space factor incl. 1/n: x1 pass [ny][nx], x2 and plane passes [nx][ny], y [ny]
     const double2* tw2;       // plane pass only: twiddles of the y lines

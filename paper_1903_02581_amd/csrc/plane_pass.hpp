@@ -84,7 +84,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
         else {
             v = a.ktab2[i - NX - NY];
             if constexpr (VK == 1) v = cmul(v, v1);
-            if (a.kconj) v = conjd(v);
         }
         TW[i] = v;
     }
@@ -176,7 +175,6 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int k2 = 0; k2 < A2; ++k2) {
                         double2 f = kt[(t + TX * ii + A1 * k2) * NY];
-                        if (a.kconj) f = conjd(f);
                         vb[q][ii * A2 + k2] = cmul(vb[q][ii * A2 + k2], f);
                     }
                 if constexpr (A2 > 1) {
@@ -228,7 +226,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                     for (int jj = 0; jj < JAX; ++jj)
 #pragma unroll
                         for (int n1 = 0; n1 < A1; ++n1) {
-                            const double2 f = vfactor<VK == 1 ? 3 : VK>(av, i1, j1, n1 * A2 + t + TX * jj, c);
+                            const double2 f = vfactor<VK == 1 ? 3 : VK, false>(av, i1, j1, n1 * A2 + t + TX * jj, c);
                             vb[q][jj * A1 + n1] = cmul(vb[q][jj * A1 + n1], f);
                         }
                 }
@@ -279,7 +277,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
                             // potential factor in real space at (x2 = row, y2)
 #pragma unroll
                             for (int n1 = 0; n1 < B1; ++n1)
-                                u[n1] = cmul(u[n1], vfactor<VK == 1 ? 3 : VK>(av, i1, j1, row, n1 * B2 + t + TY * jj));
+                                u[n1] = cmul(u[n1], vfactor<VK == 1 ? 3 : VK, false>(av, i1, j1, row, n1 * B2 + t + TY * jj));
                         }
                         dft<B1, -1>(u);
                         const int jc = t + TY * jj;
@@ -343,7 +341,7 @@ __global__ void __launch_bounds__(NT) k_plane2(const PassArgs a) {
 #pragma unroll
                     for (int n1 = 0; n1 < B1; ++n1) {
                         u[n1] = X::get(L[LY::at(row, n1)]);
-                        if constexpr (V_IN_Y) u[n1] = cmul(u[n1], vfactor<VK == 1 ? 3 : VK>(av, i1, j1, row, n1));
+                        if constexpr (V_IN_Y) u[n1] = cmul(u[n1], vfactor<VK == 1 ? 3 : VK, false>(av, i1, j1, row, n1));
                     }
                     dft<B1, -1>(u);
 #pragma unroll
