@@ -67,6 +67,13 @@ __device__ __forceinline__ void lds_barrier() {
         asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Elements per batch of the table-form potential loads: 2 on the complex64 y2
+// pass of 128- and 256-point lines (90 instead of 116 VGPRs, five waves per
+// SIMD instead of four: 256x128 y2+V 4.66 -> 4.48 ms), 4 elsewhere (the
+// complex64 x2 pass measured slower with 2: 5.21 -> 5.36 ms, 128x96 0.674 ->
+// 0.717 ms).
+constexpr int potential_batch(int axis, int n, bool c64) { return (c64 && axis == AX_Y2 && n >= 128) ? 2 : 4; }
+
 // WC > 0: the block holds WC lines, a compile-time constant (the nominal width
 // of the pass, axis3_nominal_w), so every LDS address is a per-thread base plus
 // an immediate offset; WC = 0: a.W lines, for grids that allow fewer.
@@ -157,7 +164,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             if constexpr (VK == 1) {
                 const LineTables<AXIS> tb(a, lg, t);
                 const double2 f0 = tb.fixed();
-                batched<E, 4>([&](int e) { return tb.load((e % R1) * N2 + T * (e / R1)); },
+                batched<E, potential_batch(AXIS, N, !std::is_same<S, double2>::value)>([&](int e) { return tb.load((e % R1) * N2 + T * (e / R1)); },
                               [&](int e, const VLoad& l) {
                                   const double2 f = tb.template combine<CONJ>(f0, l);
 #pragma unroll
