@@ -100,6 +100,13 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
 
     // twiddles w_n^j (and, on y axes, the kinetic factor) staged after the exchange area
     constexpr bool KT_LDS = (AXIS == AX_Y1 || AXIS == AX_Y2);
+    // persistent x1 pass: the tile's kinetic row (its lines share y1) comes from
+    // one of two LDS rows after the twiddles, written at the start of the tile
+    // from a register loaded with the previous tile's prefetch, so that no
+    // global load is issued inside the transform (a wait for one would also wait
+    // for the next tile's loads and the previous tile's stores, issued earlier)
+    constexpr bool KROW = PERS && AXIS == AX_X1;
+    const double2* krow = nullptr;
     const int LS = W + 1;  // padded LDS row: one line position across the block's W lines
     typename X::T* lds = reinterpret_cast<typename X::T*>(lds_raw);
     double2* twl = reinterpret_cast<double2*>(reinterpret_cast<char*>(lds_raw) +
@@ -239,8 +246,9 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             double2 kf[R3];
             if constexpr (!KT_LDS) {
 #pragma unroll
-                for (int k3 = 0; k3 < R3; ++k3) kf[k3] = kt[(k1 + R1 * (k2 + R2 * k3)) * kstride];
-                after_loads();
+                for (int k3 = 0; k3 < R3; ++k3)
+                    kf[k3] = KROW ? krow[k1 + R1 * (k2 + R2 * k3)] : kt[(k1 + R1 * (k2 + R2 * k3)) * kstride];
+                if constexpr (!KROW) after_loads();
             }
 #pragma unroll
             for (int s = 0; s < NST; ++s) {
@@ -351,30 +359,57 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         // elements are loaded (as stored) before the current one is transformed
         const uint32_t ntiles = a.ntiles;
         S raw[E];
+        double2 kreg = make_double2(0.0, 0.0);  // KROW: entry tid of the next tile's kinetic row
+        // the kinetic row of tile tl: y1 of its lines (a tile's lines share y1)
+        auto krow_of = [&](uint32_t tl) { return a.ktab + (int64_t)a.dnxy.div(tl * (uint32_t)W) * N; };
         uint32_t tile = blockIdx.x;
         if (tile < ntiles) {
             const LineGeom<AXIS> lg(a, tile * (uint32_t)W + (uint32_t)cl);
             walk(lg, reinterpret_cast<const S*>(a.psi) + lg.base,
                  [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
+            if constexpr (KROW) {
+                if (tid < N) kreg = krow_of(tile)[tid];
+            }
         }
-        for (; tile < ntiles; tile += gridDim.x) {
+        uint32_t it = 0;  // the block's tile count: parity selects the kinetic row
+        auto one_tile = [&](uint32_t tl) {
             // the thread's line slot and position index pass through an empty asm
             // each tile, so that the LDS and table addresses derived from them are
             // recomputed per tile rather than hoisted out of the loop and held in
             // registers for all of it
             asm volatile("" : "+v"(t), "+v"(cl));
-            const uint32_t line = tile * (uint32_t)W + (uint32_t)cl;
+            const uint32_t line = tl * (uint32_t)W + (uint32_t)cl;
             const LineGeom<AXIS> lg(a, line);
             S* ps[1] = {reinterpret_cast<S*>(a.psi) + lg.base};
 #pragma unroll
             for (int e = 0; e < E; ++e) v[0][e] = widen(raw[e]);
-            const uint32_t next = tile + gridDim.x;
+            if constexpr (KROW) {
+                // visible to every thread after the first exchange barrier; the row
+                // written two tiles ago was last read before this tile's barriers
+                double2* row = twl + N * (1 + (it & 1));
+                if (tid < N) row[tid] = kreg;
+                krow = row;
+            }
+            const uint32_t next = tl + gridDim.x;
             if (next < ntiles) {
                 const LineGeom<AXIS> ln(a, next * (uint32_t)W + (uint32_t)cl);
                 walk(ln, reinterpret_cast<const S*>(a.psi) + ln.base,
                      [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
+                if constexpr (KROW) {
+                    if (tid < N) kreg = krow_of(next)[tid];
+                }
             }
             round_trip(lg, line, ps);
+            ++it;
+        };
+        // The first tile is peeled off the loop, so that the loop is entered, like
+        // its back edge, with the next tile's loads followed by this tile's stores
+        // outstanding: the wait for those loads (the memory counter covers loads
+        // and stores in issue order) then leaves the stores in flight, where a
+        // loop entered with the loads alone outstanding waits for everything.
+        if (tile < ntiles) {
+            one_tile(tile);
+            for (tile += gridDim.x; tile < ntiles; tile += gridDim.x) one_tile(tile);
         }
     } else {
         const uint32_t line = blockIdx.x * (uint32_t)W + (uint32_t)cl;

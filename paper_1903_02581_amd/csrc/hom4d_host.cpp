@@ -148,11 +148,14 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         if (axis == AX_X2) w = std::min<int64_t>(w, ilog2_pow2_divisor(ny));
         if (axis == AX_Y2 && grad) w = std::min<int64_t>(w, ilog2_pow2_divisor(nx));
         p.W = (int)std::max<int64_t>(w, 1);
-        p.lds = axis3_lds_bytes(p.n, p.W, nst, mixed);
         // persistent form on the complex64 x1 and y1 passes of 128- and 256-point
         // lines (256x128: x1 6.07 -> 5.36 ms, y1 4.46 -> 4.20 ms); the other
-        // passes, FP64 and 96-point lines measured slower that way
+        // passes, FP64 and 96-point lines measured slower that way.  The x1 form
+        // stages each tile's kinetic row, so a tile's lines share y1 and the
+        // block's threads cover a row.
         p.pers = mixed && nst == 1 && !grad && p.n >= 128 && (axis == AX_X1 || axis == AX_Y1);
+        if (p.pers && axis == AX_X1 && (nxy % p.W != 0 || (int64_t)p.t * p.W < p.n)) p.pers = false;
+        p.lds = axis3_pass_lds_bytes(axis, p.n, p.W, nst, mixed, p.pers);
         return p;
     }
     int64_t w = 256 / sh.t;

@@ -120,6 +120,11 @@ __host__ __device__ constexpr size_t axis3_xchg_bytes(int n, int w, int nst, boo
 __host__ __device__ constexpr size_t axis3_lds_bytes(int n, int w, int nst, bool c64) {
     return axis3_xchg_bytes(n, w, nst, c64) + 2u * (size_t)n * 16u;
 }
+// ... of a pass: the persistent x1 pass keeps two kinetic rows after its
+// twiddles, one more row of n complex128 entries
+__host__ __device__ constexpr size_t axis3_pass_lds_bytes(int axis, int n, int w, int nst, bool c64, bool pers) {
+    return axis3_lds_bytes(n, w, nst, c64) + ((pers && axis == AX_X1) ? (size_t)n * 16u : 0u);
+}
 
 // Launch one per-axis pass: blocks of t*W threads, nlines/W blocks; with pers
 // (three-stage forward x1 and y1 passes only) the persistent form, as many

@@ -282,7 +282,7 @@ hipError_t launch_axis(int axis, int n, bool mixed, int nst, bool pers, const Pa
     const int max_threads = axis3_threads(n, nst) > 0 ? axis3_block_threads(axis, n, nst, mixed) : 256;
     if (nblocks > 0x7fffffff || t * a.W > max_threads || lds_bytes > 160 * 1024) return hipErrorInvalidValue;
     if (axis3_threads(n, nst) > 0) {
-        if (lds_bytes < axis3_lds_bytes(n, a.W, nst, mixed)) return hipErrorInvalidValue;
+        if (lds_bytes < axis3_pass_lds_bytes(axis, n, a.W, nst, mixed, pers)) return hipErrorInvalidValue;
     } else {
         FftShape sh;
         if (!fft_shape(n, &sh)) return hipErrorInvalidValue;
