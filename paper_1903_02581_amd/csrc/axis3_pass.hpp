@@ -30,7 +30,10 @@
 // of the 256x128 state (x1 6.07 -> 5.36 ms, y1 4.46 -> 4.20 ms); the x2 and
 // y2 passes, the FP64 passes and n = 96 lines ran slower that way (128x96
 // complex64 y1 0.52 -> 0.61 ms, y2 0.72 -> 0.86 ms; 128x128 FP64 x1 1.62 ->
-// 1.79 ms), so they keep one tile per block.
+// 1.79 ms), so they keep one tile per block.  No global load is waited for
+// inside a tile's transform (the x1 pass takes its kinetic factors from LDS),
+// and the first tile is peeled off the loop, so that the only wait for the
+// prefetch, at the start of the next tile, leaves the stores in flight.
 //
 // The arithmetic is FP64 for both storage types.  With complex64 storage the
 // exchange area holds complex64 too: each exchange then rounds like one more
