@@ -11,7 +11,8 @@ factors applied literally one after the other (no merging of half steps).
 
 Source: L. Bellentani, P. Bordone, X. Oriols, A. Bertoni, arXiv 1903.02581,
 Sec. II.C Eq. (evoloperat) and Appendix A (split-step Fourier method for two
-particles), Sec. III Eq. (p_bunching) (bunching probability), Sec. III.B
+particles), Sec. III Eq. (p_bunching) (bunching probability), Sec. II.A Eq. (H_effective)
+and Sec. II.B Eq. (singlepwp) (edge states and edge-state wave packets), Sec. III.B
 Eq. (coulomb) and Eq. (screenedCoulomb), Sec. III.C Eq. (reduced_density)
 (spatial entanglement).
 
@@ -25,3 +26,4 @@ from .splitstep import (Grid, make_grid, theta_x, theta_y, theta_v, apply_x, app
 from .observables import (observables, entanglement, region_weights_4d, marginal, conditional,  # noqa
                           orbital_observables)
 from .adjoint import loss_and_grad_stored, grad_fd  # noqa
+from .edge_states import lowest_edge_states, edge_packet  # noqa
