@@ -216,6 +216,25 @@ int hom4d_marginal(hom4d* h, double* out);
  * Synchronises. */
 int hom4d_conditional(hom4d* h, int32_t ix2, int32_t jy2, double* out);
 
+/* One electron's Gaussian edge-state wave packet on the handle's grid, the
+ * input of hom4d_init_state (Sec. II.A, Eq. (H_effective); Sec. II.B,
+ * Eq. (singlepwp)).  For every grid wave number k along x the lowest
+ * eigenpair of the transverse Hamiltonian
+ *     H(k) = kappa [ -d^2/dy^2 + (k - y eB/hbar)^2 ] + v_col(y)
+ * (gauge A = (-B y, 0), second derivative spectral on the periodic y grid) is
+ * found on the GPU (Jacobi, FP64), its sign fixed so that the largest-magnitude
+ * component is positive; k0 is the wave number, among k > 0 (top = 1) or k < 0
+ * (top = 0), whose level is closest to hbar omega_c / 2 + e_above_lll_mev; and
+ *     psi(x, y) = sum_k exp(-sigma_x^2 (k - k0)^2) exp(i k (x - xc)) phi_k(y),
+ * normalised on the grid.  v_col: host [ny] FP64 meV (the potential across the
+ * edge where the packet starts), copied.  psi_out: host [nx][ny] interleaved
+ * complex128.  info_out (may be NULL): host double[3] = (k0 in 1/nm, its level
+ * in meV, the target level in meV).  The handle's state is not touched.  EINVAL
+ * on NULL pointers, sigma_x <= 0, non-finite inputs or top not 0/1; EHIP
+ * (allocates a work buffer of 2 nx ny^2 doubles for the call).  Synchronises. */
+int hom4d_edge_packet(hom4d* h, const double* v_col, double sigma_x_nm, double xc_nm, int32_t top,
+                      double e_above_lll_mev, double* psi_out, double* info_out);
+
 /* Gather the (n1 x n2) slice above into host memory (interleaved complex128),
  * unnormalised.  Synchronises. */
 int hom4d_gather_slice(hom4d* h, const int32_t* ix1, int32_t n1, int32_t jy1,

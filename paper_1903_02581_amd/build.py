@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["hom4d_host.cpp", "hom4d_kernels.hip", "axis_f64_1.hip", "axis_f64_2.hip",
            "axis_f32_1.hip", "axis_f32_2.hip", "axis3_f64.hip", "axis3_f32.hip", "plane_f64.hip",
-           "plane_f32.hip"]
+           "plane_f32.hip", "edge_states.hip"]
 
 ARCH = os.environ.get("HOM4D_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

@@ -1303,6 +1303,73 @@ int hom4d_pass_plan(hom4d* h) {
     return use_plane(h) ? 3 : 4;
 }
 
+int hom4d_edge_packet(hom4d* h, const double* v_col, double sigma_x_nm, double xc_nm, int32_t top,
+                      double e_above_lll_mev, double* psi_out, double* info_out) {
+    if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
+    if (!v_col || !psi_out) return fail(HOM4D_EINVAL, "v_col and psi_out must not be NULL");
+    if (!(sigma_x_nm > 0.0) || !std::isfinite(sigma_x_nm) || !std::isfinite(xc_nm) ||
+        !std::isfinite(e_above_lll_mev))
+        return fail(HOM4D_EINVAL, "sigma_x=%g must be positive and finite, xc=%g and e_above=%g finite",
+                    sigma_x_nm, xc_nm, e_above_lll_mev);
+    if (top != 0 && top != 1) return fail(HOM4D_EINVAL, "top=%d must be 0 or 1", top);
+    const hom4d_cfg& c = h->cfg;
+    const int nx = c.nx, ny = c.ny;
+    for (int j = 0; j < ny; ++j)
+        if (!std::isfinite(v_col[j])) return fail(HOM4D_EINVAL, "v_col[%d] is not finite", j);
+    // first row of the spectral kinetic matrix kappa (-d^2/dy^2) on the periodic y grid
+    std::vector<double> host((size_t)2 * ny + nx);
+    double* circ = host.data();
+    for (int d = 0; d < ny; ++d) {
+        double acc = 0.0;
+        for (int m = 0; m < ny; ++m) {
+            const double k = kgrid(ny, c.ly_nm, m);
+            acc += k * k * std::cos(2.0 * M_PI * (double)((m * d) % ny) / ny);
+        }
+        circ[d] = h->u.kappa * acc / ny;
+    }
+    std::memcpy(host.data() + ny, v_col, ny * sizeof(double));
+    for (int m = 0; m < nx; ++m) host[2 * ny + m] = kgrid(nx, c.lx_nm, m);
+    // device: circ, v, kx | work 2 nx ny^2 | e1 nx | phi nx ny | psi 2 nx ny | part nx | info 3
+    const size_t n_in = host.size(), n_work = (size_t)2 * nx * ny * ny;
+    const size_t total = n_in + n_work + nx + (size_t)nx * ny + (size_t)2 * nx * ny + nx + 3;
+    double* dev = nullptr;
+    HIP_TRY(hipMalloc((void**)&dev, total * sizeof(double)));
+    EdgeArgs e{};
+    e.circ = dev;
+    e.vcol = dev + ny;
+    e.kx = dev + 2 * ny;
+    e.work = dev + n_in;
+    e.e1 = e.work + n_work;
+    e.phi = e.e1 + nx;
+    e.psi = reinterpret_cast<double2*>(e.phi + (size_t)nx * ny);
+    e.part = e.phi + (size_t)nx * ny + (size_t)2 * nx * ny;
+    e.info = e.part + nx;
+    e.nx = nx;
+    e.ny = ny;
+    e.top = top;
+    e.kappa = h->u.kappa;
+    e.inv_lb2 = h->u.eoh * c.b_tesla;
+    e.x0 = xgrid(c, 0);
+    e.dx = c.lx_nm / nx;
+    e.y0 = ygrid(c, 0);
+    e.dy = c.ly_nm / ny;
+    e.target = h->u.kappa * e.inv_lb2 + e_above_lll_mev;  // hbar omega_c / 2 = kappa eB / hbar
+    e.sigma = sigma_x_nm;
+    e.xc = xc_nm;
+    double info[3] = {0.0, 0.0, 0.0};
+    hipError_t err = hipMemcpyAsync(dev, host.data(), n_in * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (err == hipSuccess) err = launch_edge_packet(e, h->stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(psi_out, e.psi, (size_t)nx * ny * sizeof(double2), hipMemcpyDeviceToHost, h->stream);
+    if (err == hipSuccess) err = hipMemcpyAsync(info, e.info, sizeof(info), hipMemcpyDeviceToHost, h->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
+    const hipError_t ferr = hipFree(dev);
+    if (err != hipSuccess) return fail(HOM4D_EHIP, "edge packet: %s", hipGetErrorString(err));
+    if (ferr != hipSuccess) return fail(HOM4D_EHIP, "edge packet: %s", hipGetErrorString(ferr));
+    if (info_out) std::memcpy(info_out, info, sizeof(info));
+    return HOM4D_OK;
+}
+
 int hom4d_run_pass(hom4d* h, int32_t axis, int32_t reps) {
     if (!h) return fail(HOM4D_EINVAL, "handle is NULL");
     if (axis < 0 || axis > 5) return fail(HOM4D_EINVAL, "axis=%d must be 0..5", axis);

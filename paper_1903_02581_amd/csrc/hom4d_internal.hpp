@@ -161,6 +161,27 @@ hipError_t launch_grad_finish(const double* m_x2, int bpr_x2, const double* m_y2
                               double* dldv, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 
+// Edge states of every grid wave number along x and one Gaussian edge-state
+// packet built from them (edge_states.hip).  Device pointers: circ [ny] (first
+// row of the spectral kinetic matrix), vcol [ny], kx [nx], work [2 nx ny^2],
+// e1 [nx], phi [nx ny], psi [nx ny], part [nx], info [3] = (k0, E(k0), target).
+struct EdgeArgs {
+    const double* circ;
+    const double* vcol;
+    const double* kx;
+    int nx, ny, top;
+    double kappa, inv_lb2;   // meV nm^2, eB/hbar in 1/nm^2
+    double x0, dx, y0, dy;   // grids (nm)
+    double target, sigma, xc;
+    double* work;
+    double* e1;
+    double* phi;
+    double2* psi;
+    double* part;
+    double* info;
+};
+hipError_t launch_edge_packet(const EdgeArgs& e, hipStream_t s);
+
 // Fixed device scratch of the no-allocation reverse sweep: kScratchDoubles
 // FP64 values (64 MiB) per GPU.  init_scratch(device), with that device
 // current, takes the array's address on it once; scratch_on(device) returns

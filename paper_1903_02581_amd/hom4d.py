@@ -31,7 +31,7 @@ EXPORTS = ["hom4d_create", "hom4d_destroy", "hom4d_validate_cfg", "hom4d_state_b
            "hom4d_load_state", "hom4d_store_state", "hom4d_checkpoint_bytes",
            "hom4d_save_checkpoint", "hom4d_load_checkpoint", "hom4d_step", "hom4d_observables",
            "hom4d_set_norm_tol", "hom4d_entanglement", "hom4d_gather_slice", "hom4d_marginal",
-           "hom4d_conditional", "hom4d_grad_begin",
+           "hom4d_conditional", "hom4d_edge_packet", "hom4d_grad_begin",
            "hom4d_grad_backward", "hom4d_grad_backward_noalloc", "hom4d_grad_end", "hom4d_run_pass", "hom4d_set_pass_plan",
            "hom4d_pass_plan", "hom4d_pass_timing", "hom4d_pass_times", "hom4d_strerror",
            "hom4d_last_error"]
@@ -91,6 +91,7 @@ def load_library(path: str | None = None) -> ctypes.CDLL:
         "hom4d_gather_slice": ([vp, i32p, c_int32, c_int32, i32p, c_int32, c_int32, dp], c_int),
         "hom4d_marginal": ([vp, dp], c_int),
         "hom4d_conditional": ([vp, c_int32, c_int32, dp], c_int),
+        "hom4d_edge_packet": ([vp, dp, c_double, c_double, c_int32, c_double, dp, dp], c_int),
         "hom4d_grad_begin": ([vp, c_int32, vp, c_size_t], c_int),
         "hom4d_grad_backward": ([vp, dp, dp, vp, dp, dp, dp], c_int),
         "hom4d_grad_backward_noalloc": ([vp, dp, dp, vp, dp, dp, dp], c_int),
@@ -285,6 +286,21 @@ class Propagator:
         self._check(self.lib.hom4d_conditional(self.h, int(ix2), int(jy2), _dptr(out)),
                     "conditional")
         return out
+
+    def edge_packet(self, v_col, sigma_x: float, xc: float, top: bool, e_above_lll: float):
+        """One electron's Gaussian edge-state packet on this grid, built on the GPU
+        (Eq. (H_effective), Eq. (singlepwp)): shape [nx, ny] complex128, and
+        dict(k0, e1_k0, target)."""
+        v = np.ascontiguousarray(v_col, dtype=np.float64)
+        if v.shape != (self.ny,):
+            raise ValueError(f"v_col must have shape ({self.ny},)")
+        out = np.empty((self.nx, self.ny), dtype=np.complex128)
+        info = np.zeros(3, dtype=np.float64)
+        self._check(self.lib.hom4d_edge_packet(self.h, _dptr(v), float(sigma_x), float(xc),
+                                               1 if top else 0, float(e_above_lll),
+                                               _dptr(out.view(np.float64)), _dptr(info)),
+                    "edge_packet")
+        return out, dict(k0=float(info[0]), e1_k0=float(info[1]), target=float(info[2]))
 
     # ---------------------------------------------------------------- adjoint
     def grad_begin(self, ckpt_every: int, steps: int):
