@@ -16,8 +16,9 @@ and Sec. II.B Eq. (singlepwp) (edge states and edge-state wave packets), Sec. II
 Eq. (coulomb) and Eq. (screenedCoulomb), Sec. III.C Eq. (reduced_density)
 (spatial entanglement).
 
-Pins: every function here is checked in tests/test_oracle_pins.py against
-closed forms, invariants, dense matrix exponentials or finite differences.
+Pins: every function here is checked in tests/test_oracle_pins.py (the edge
+states in tests/test_oracle_edge.py) against closed forms, invariants, dense
+matrix exponentials or finite differences.
 Parity status per function is listed in each module docstring.
 """
 from .splitstep import (Grid, make_grid, theta_x, theta_y, theta_v, apply_x, apply_y,  # noqa
