@@ -379,11 +379,14 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             // the thread's line slot and position index pass through an empty asm
             // each tile, so that the LDS and table addresses derived from them are
             // recomputed per tile rather than hoisted out of the loop and held in
-            // registers for all of it; the 1024-thread blocks, one per CU whatever
-            // their registers (up to 128), keep them hoisted instead (256x128
-            // x1: 96 -> 120 VGPRs, about 8 fewer VALU instructions per point)
-            if constexpr (axis3_block_threads(AXIS, N, NST, !std::is_same<S, double2>::value) != 1024)
-                asm volatile("" : "+v"(t), "+v"(cl));
+            // registers for all of it; the 256-point x1 pass (1024-thread blocks,
+            // one per CU whatever their registers up to 128) and the 128-point y1
+            // pass (512-thread blocks, two per CU at up to 128 registers) keep them
+            // hoisted instead: 256x128 x1 96 -> 120 VGPRs, about 8 fewer VALU
+            // instructions per point, 5.25 -> 5.12 ms; y1 with 32-line blocks
+            // 4.28 -> 3.89 ms
+            constexpr bool HOIST = WC > 0 && ((AXIS == AX_X1 && N == 256) || (AXIS == AX_Y1 && N == 128));
+            if constexpr (!HOIST) asm volatile("" : "+v"(t), "+v"(cl));
             const uint32_t line = tl * (uint32_t)W + (uint32_t)cl;
             const LineGeom<AXIS> lg(a, line);
             S* ps[1] = {reinterpret_cast<S*>(a.psi) + lg.base};
