@@ -2,7 +2,8 @@
 //
 // X[k] = sum_n v[n] w^(n k), w = exp(DIR * 2 pi i / R); DIR = -1 is the forward
 // transform (exp(-i k x) convention), DIR = +1 the unnormalised inverse.
-// Sizes R in {1, 2, 3, 4, 6, 8, 12, 16, 24}; composite sizes use one
+// Sizes R in {1, 2, 3, 4, 6, 8, 12, 16, 24}; 8 is two 4-point transforms and a
+// radix-2 step; the other composite sizes use one
 // Cooley-Tukey split R = A * B (A = 4, 2 or 3) with compile-time twiddles, so
 // after unrolling every index and constant is known to the compiler.
 #pragma once
@@ -99,10 +100,11 @@ __device__ __forceinline__ void dft3(double2* v) {
     const double2 s = cadd(v[1], v[2]);
     const double2 d = csub(v[1], v[2]);
     const double2 m = make_double2(fma(-0.5, s.x, a.x), fma(-0.5, s.y, a.y));
-    const double2 t = cscale(imul<DIR>(d), h);
+    // the scaling by h folds into the output additions
+    const double2 t = imul<DIR>(d);
     v[0] = cadd(a, s);
-    v[1] = cadd(m, t);
-    v[2] = csub(m, t);
+    v[1] = make_double2(fma(h, t.x, m.x), fma(h, t.y, m.y));
+    v[2] = make_double2(fma(-h, t.x, m.x), fma(-h, t.y, m.y));
 }
 
 template <int DIR>
@@ -116,6 +118,35 @@ __device__ __forceinline__ void dft4(double2* v) {
     v[3] = csub(d0, id1);
 }
 
+// 8 points from the 4-point transforms E, O of the even and odd elements:
+// X[k] = E[k] + w^k O[k], X[k + 4] = E[k] - w^k O[k].  The odd multiples of 45
+// degrees, w^1 = c (1 + DIR i) and w^3 = -c (1 - DIR i) with c = cos(pi / 4), take
+// two additions each, and their scaling by c folds into the fused multiply-adds
+// of the output pair (52 instead of 56 FP64 operations).
+template <int DIR>
+__device__ __forceinline__ void dft8(double2* v) {
+    constexpr double c = 0.7071067811865476;
+    double2 e[4] = {v[0], v[2], v[4], v[6]};
+    double2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<DIR>(e);
+    dft4<DIR>(o);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    const double2 t2 = imul<DIR>(o[2]);
+    v[2] = cadd(e[2], t2);
+    v[6] = csub(e[2], t2);
+    // w^1 (a + i b) = c (a - DIR b + i (b + DIR a))
+    const double r1 = DIR < 0 ? o[1].x + o[1].y : o[1].x - o[1].y;
+    const double i1 = DIR < 0 ? o[1].y - o[1].x : o[1].y + o[1].x;
+    v[1] = make_double2(fma(c, r1, e[1].x), fma(c, i1, e[1].y));
+    v[5] = make_double2(fma(-c, r1, e[1].x), fma(-c, i1, e[1].y));
+    // w^3 (a + i b) = -c (a + DIR b + i (b - DIR a))
+    const double r3 = DIR < 0 ? o[3].x - o[3].y : o[3].x + o[3].y;
+    const double i3 = DIR < 0 ? o[3].y + o[3].x : o[3].y - o[3].x;
+    v[3] = make_double2(fma(-c, r3, e[3].x), fma(-c, i3, e[3].y));
+    v[7] = make_double2(fma(c, r3, e[3].x), fma(c, i3, e[3].y));
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft(double2* v) {
     if constexpr (R == 1) {
@@ -126,6 +157,8 @@ __device__ __forceinline__ void dft(double2* v) {
         dft3<DIR>(v);
     } else if constexpr (R == 4) {
         dft4<DIR>(v);
+    } else if constexpr (R == 8) {
+        dft8<DIR>(v);
     } else {
         // n = B * na + nb, k = ka + A * kb:
         //   u[nb][ka] = DFT_A over na of v[B na + nb], times w_R^(nb ka);
