@@ -1073,10 +1073,11 @@ int hom4d_step(hom4d* h, int64_t n) {
     // recording: every checkpoint these n steps reach must fit the pool, checked
     // before anything runs, so that a refused call leaves the state, the step
     // count and the recording as they were
-    const int64_t last_slot = (h->rec_steps + n) / h->ckpt_every;
-    if ((size_t)(last_slot + 1) * h->state_bytes > h->pool_bytes)
-        return fail(HOM4D_ENOMEM, "checkpoint %lld does not fit the pool (%zu bytes)", (long long)last_slot,
-                    h->pool_bytes);
+    // (counted in whole slots, so that no product can wrap)
+    const int64_t slots = (int64_t)(h->pool_bytes / h->state_bytes);
+    if (n > INT64_MAX - h->rec_steps || (h->rec_steps + n) / h->ckpt_every >= slots)
+        return fail(HOM4D_ENOMEM, "the checkpoints of %lld more recorded steps do not fit the pool (%zu bytes)",
+                    (long long)n, h->pool_bytes);
     // close the state on every checkpoint boundary and copy it out; a failure
     // part way closes the recording (its checkpoints no longer match the state)
     int64_t left = n;

@@ -66,7 +66,9 @@ def test_recording_refuses_steps_past_the_pool():
     p.step(4)
     before = p.store_state()
     step_before = p.observables(w.w_top)["step"]
-    for n in (4, 100):                    # 8 and 104 recorded steps would reach slots 4 and 52
+    # 8 and 104 recorded steps would reach slots 4 and 52; 2^62 and 2^63 - 1 more steps would
+    # overflow a byte count or the step count itself
+    for n in (4, 100, 2 ** 62, 2 ** 63 - 1):
         with pytest.raises(Hom4dError) as e:
             p.step(n)
         assert e.value.status == -4
