@@ -21,7 +21,8 @@
 //
 // PERS (forward one-state passes only): the kernel is persistent: a block
 // walks tiles of W lines (tile = blockIdx.x, + gridDim.x, ...) and issues the
-// loads of its next tile before it transforms the current one, so that the HBM
+// loads of its next tile while it transforms the current one (at its start, or
+// on the wide forms in four parts between its exchanges), so that the HBM
 // reads of one tile overlap the arithmetic and LDS exchanges of the previous
 // one inside the block, instead of relying on other resident blocks being out
 // of phase.  Its exchanges synchronise the block on LDS alone (lds_barrier),
@@ -152,11 +153,21 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         }
     };
 
+    // elements e0 .. e1 - 1 of the walk above, each address formed directly
+    auto walk_part = [&](const LineGeom<AXIS>& lg, auto* base, int e0, int e1, auto&& fn) {
+#pragma unroll
+        for (int e = e0; e < e1; ++e) {
+            const int jj = e / R1, n1 = e % R1;
+            fn(e, base + ((int64_t)(t + T * jj) + (int64_t)n1 * N2) * lg.sN);
+        }
+    };
+
     // Transform round trip of the block's tile held in v (loaded elements in,
     // the same elements out, stored in place), with the potential factor and
-    // the reverse sweep's gradient terms.
+    // the reverse sweep's gradient terms.  between(k) runs after the k-th of the
+    // four exchanges (k = 0..3).
     double2 v[NST][E];
-    auto round_trip = [&](const LineGeom<AXIS>& lg, uint32_t line, S* const* ps) {
+    auto round_trip = [&](const LineGeom<AXIS>& lg, uint32_t line, S* const* ps, auto&& between) {
         // gradient accumulators of the reverse sweep: the potential marginal
         // Im(conj(lambda) psi) on the side of the potential factor the pass is told
         // to take it (before: G_MIN, after: G_MOUT), and the dL/dB term of the x
@@ -215,6 +226,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 for (int k1 = 0; k1 < R1; ++k1) Lw(s, k1 * N2 + jc, v[s][jj * R1 + k1]);
             }
         sync();
+        between(0);
 
         // ---- stage B1 (forward), in place on its positions
 #pragma unroll
@@ -231,6 +243,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 for (int k2 = 0; k2 < R2; ++k2) Lw(s, k1 * N2 + k2 * R3 + j3, v[s][ii * R2 + k2]);
             }
         sync();
+        between(1);
 
         // ---- stage B2: forward, kinetic phase at k = k1 + R1 (k2 + R2 k3), inverse
         // x kinetic factor table: y-major [y][k] on the x1 pass, k-major [k][y] on the x2 pass
@@ -288,6 +301,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             }
         }
         sync();
+        between(2);
 
         // ---- stage B1 (inverse)
 #pragma unroll
@@ -304,6 +318,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 for (int n2 = 0; n2 < R2; ++n2) Lw(s, k1 * N2 + n2 * R3 + j3, v[s][ii * R2 + n2]);
             }
         sync();
+        between(3);
 
         // ---- stage A (inverse), back on the loaded elements
 #pragma unroll
@@ -375,18 +390,23 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             }
         }
         uint32_t it = 0;  // the block's tile count: parity selects the kinetic row
+        // The wide persistent forms -- the 256-point x1 pass (1024-thread blocks,
+        // one per CU whatever their registers up to 128) and the 128-point y1 pass
+        // (32-line 512-thread blocks, two per CU at up to 128 registers) -- keep
+        // the thread's tile-invariant addresses in registers, and issue the next
+        // tile's loads in four parts, one after each exchange of the current tile,
+        // instead of all at its start.  Elsewhere the thread's line slot and
+        // position index pass through an empty asm each tile, so that the LDS and
+        // table addresses derived from them are recomputed per tile rather than
+        // hoisted out of the loop and held in registers for all of it, and the
+        // loads go out at once.  Hoisting: 256x128 x1 96 -> 120 VGPRs, about 8
+        // fewer VALU instructions per point, 5.25 -> 5.12 ms; y1 with 32-line
+        // blocks 4.28 -> 3.89 ms.  Spreading: x1 120 -> 116 VGPRs, 5.08 -> 4.48-4.67
+        // ms, y1 120 -> 104 VGPRs, 3.79 -> 3.59 ms (the 128-point x1 pass of the
+        // 128x96 state measured 0.549 -> 0.554 ms that way and loads at once).
+        constexpr bool WIDE = WC > 0 && ((AXIS == AX_X1 && N == 256) || (AXIS == AX_Y1 && N == 128));
         auto one_tile = [&](uint32_t tl) {
-            // the thread's line slot and position index pass through an empty asm
-            // each tile, so that the LDS and table addresses derived from them are
-            // recomputed per tile rather than hoisted out of the loop and held in
-            // registers for all of it; the 256-point x1 pass (1024-thread blocks,
-            // one per CU whatever their registers up to 128) and the 128-point y1
-            // pass (512-thread blocks, two per CU at up to 128 registers) keep them
-            // hoisted instead: 256x128 x1 96 -> 120 VGPRs, about 8 fewer VALU
-            // instructions per point, 5.25 -> 5.12 ms; y1 with 32-line blocks
-            // 4.28 -> 3.89 ms
-            constexpr bool HOIST = WC > 0 && ((AXIS == AX_X1 && N == 256) || (AXIS == AX_Y1 && N == 128));
-            if constexpr (!HOIST) asm volatile("" : "+v"(t), "+v"(cl));
+            if constexpr (!WIDE) asm volatile("" : "+v"(t), "+v"(cl));
             const uint32_t line = tl * (uint32_t)W + (uint32_t)cl;
             const LineGeom<AXIS> lg(a, line);
             S* ps[1] = {reinterpret_cast<S*>(a.psi) + lg.base};
@@ -400,15 +420,30 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 krow = row;
             }
             const uint32_t next = tl + gridDim.x;
-            if (next < ntiles) {
-                const LineGeom<AXIS> ln(a, next * (uint32_t)W + (uint32_t)cl);
-                walk(ln, reinterpret_cast<const S*>(a.psi) + ln.base,
-                     [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
+            if constexpr (WIDE) {
+                const bool has_next = next < ntiles;
+                const LineGeom<AXIS> ln(a, (has_next ? next : tl) * (uint32_t)W + (uint32_t)cl);
+                const S* nbase = reinterpret_cast<const S*>(a.psi) + ln.base;
                 if constexpr (KROW) {
-                    if (tid < N) kreg = krow_of(next)[tid];
+                    if (has_next && tid < N) kreg = krow_of(next)[tid];
                 }
+                constexpr int PART = (E + 3) / 4;
+                round_trip(lg, line, ps, [&](int k) {
+                    if (has_next)
+                        walk_part(ln, nbase, k * PART, (k + 1) * PART < E ? (k + 1) * PART : E,
+                                  [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
+                });
+            } else {
+                if (next < ntiles) {
+                    const LineGeom<AXIS> ln(a, next * (uint32_t)W + (uint32_t)cl);
+                    walk(ln, reinterpret_cast<const S*>(a.psi) + ln.base,
+                         [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
+                    if constexpr (KROW) {
+                        if (tid < N) kreg = krow_of(next)[tid];
+                    }
+                }
+                round_trip(lg, line, ps, [](int) {});
             }
-            round_trip(lg, line, ps);
             ++it;
         };
         // The first tile is peeled off the loop, so that the loop is entered, like
@@ -435,7 +470,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         for (int s = 0; s < NST; ++s)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[s][e] = widen(raw[s][e]);
-        round_trip(lg, line, ps);
+        round_trip(lg, line, ps, [](int) {});
     }
 }
 
