@@ -401,9 +401,10 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         // hoisted out of the loop and held in registers for all of it, and the
         // loads go out at once.  Hoisting: 256x128 x1 96 -> 120 VGPRs, about 8
         // fewer VALU instructions per point, 5.25 -> 5.12 ms; y1 with 32-line
-        // blocks 4.28 -> 3.89 ms.  Spreading: x1 120 -> 116 VGPRs, 5.08 -> 4.48-4.67
-        // ms, y1 120 -> 104 VGPRs, 3.79 -> 3.59 ms (the 128-point x1 pass of the
-        // 128x96 state measured 0.549 -> 0.554 ms that way and loads at once).
+        // blocks 4.28 -> 3.89 ms.  Spreading (the schedule below), 256x128: x1
+        // 5.10 -> 4.41 ms, y1 3.83 -> 3.57-3.62 ms, with fewer registers held over
+        // the tile (the 128-point x1 pass of the 128x96 state measured 0.549 ->
+        // 0.554 ms with four parts and loads at once).
         constexpr bool WIDE = WC > 0 && ((AXIS == AX_X1 && N == 256) || (AXIS == AX_Y1 && N == 128));
         auto one_tile = [&](uint32_t tl) {
             if constexpr (!WIDE) asm volatile("" : "+v"(t), "+v"(cl));
@@ -427,12 +428,23 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 if constexpr (KROW) {
                     if (has_next && tid < N) kreg = krow_of(next)[tid];
                 }
-                constexpr int PART = (E + 3) / 4;
-                round_trip(lg, line, ps, [&](int k) {
-                    if (has_next)
-                        walk_part(ln, nbase, k * PART, (k + 1) * PART < E ? (k + 1) * PART : E,
+                // NP parts of the E elements, part j issued at slot FIRST + j (slot -1:
+                // before the first stage, slot k >= 0: after exchange k): x1 in four
+                // parts from the start of the tile, y1 in two after its first two
+                // exchanges, the fastest of the schedules measured (x1 four parts
+                // after the four exchanges 4.56-4.65 ms, three or two from the start
+                // 4.62 and 4.76 ms; y1 four parts 3.59-3.68 ms)
+                constexpr int NP = AXIS == AX_X1 ? 4 : 2;
+                constexpr int FIRST = AXIS == AX_X1 ? -1 : 0;
+                constexpr int PART = (E + NP - 1) / NP;
+                auto part = [&](int slot) {
+                    const int j = slot - FIRST;
+                    if (has_next && j >= 0 && j < NP)
+                        walk_part(ln, nbase, j * PART, (j + 1) * PART < E ? (j + 1) * PART : E,
                                   [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
-                });
+                };
+                part(-1);
+                round_trip(lg, line, ps, part);
             } else {
                 if (next < ntiles) {
                     const LineGeom<AXIS> ln(a, next * (uint32_t)W + (uint32_t)cl);
