@@ -394,8 +394,8 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         // one per CU whatever their registers up to 128) and the 128-point y1 pass
         // (32-line 512-thread blocks, two per CU at up to 128 registers) -- keep
         // the thread's tile-invariant addresses in registers, and issue the next
-        // tile's loads in four parts, one after each exchange of the current tile,
-        // instead of all at its start.  Elsewhere the thread's line slot and
+        // tile's loads in parts while the current tile is transformed, instead of
+        // all at its start (the schedule below).  Elsewhere the thread's line slot and
         // position index pass through an empty asm each tile, so that the LDS and
         // table addresses derived from them are recomputed per tile rather than
         // hoisted out of the loop and held in registers for all of it, and the
