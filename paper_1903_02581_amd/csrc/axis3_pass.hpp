@@ -391,8 +391,8 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         }
         uint32_t it = 0;  // the block's tile count: parity selects the kinetic row
         // The wide persistent forms -- the 256-point x1 pass (1024-thread blocks,
-        // one per CU whatever their registers up to 128) and the 128-point y1 pass
-        // (32-line 512-thread blocks, two per CU at up to 128 registers) -- keep
+        // one per CU whatever their registers up to 128) and the 128-point x1 and
+        // y1 passes (32-line 512-thread blocks, two per CU at up to 128 registers) -- keep
         // the thread's tile-invariant addresses in registers, and issue the next
         // tile's loads in parts while the current tile is transformed, instead of
         // all at its start (the schedule below).  Elsewhere the thread's line slot and
@@ -403,9 +403,11 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         // fewer VALU instructions per point, 5.25 -> 5.12 ms; y1 with 32-line
         // blocks 4.28 -> 3.89 ms.  Spreading (the schedule below), 256x128: x1
         // 5.10 -> 4.41 ms, y1 3.83 -> 3.57-3.62 ms, with fewer registers held over
-        // the tile (the 128-point x1 pass of the 128x96 state measured 0.549 ->
-        // 0.554 ms with four parts and loads at once).
-        constexpr bool WIDE = WC > 0 && ((AXIS == AX_X1 && N == 256) || (AXIS == AX_Y1 && N == 128));
+        // the tile; the 128-point x1 pass in 32-line blocks, hoisted and in four
+        // parts from the start: 128x96 0.559 -> 0.526 ms, 128x64 0.279 -> 0.234 ms
+        // (its 16-line blocks measured 0.549 -> 0.554 ms in four parts and
+        // loads at once).
+        constexpr bool WIDE = WC > 0 && ((AXIS == AX_X1 && (N == 256 || N == 128)) || (AXIS == AX_Y1 && N == 128));
         auto one_tile = [&](uint32_t tl) {
             if constexpr (!WIDE) asm volatile("" : "+v"(t), "+v"(cl));
             const uint32_t line = tl * (uint32_t)W + (uint32_t)cl;

@@ -142,9 +142,10 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         p.t = t3;
         // The complex64 x2 pass at n = 128 takes 32 lines as well (512 threads,
         // complex64 entries within 80 KB): x2+V 842 -> 812 us at 128 x 96, 317 ->
-        // 310 us at 128 x 64 (the x1 pass measured slower that way, 581 -> 647);
-        // so does the persistent y1 pass, with its addresses kept in registers
-        // (256 x 128: 4.28 -> 3.83 ms).
+        // 310 us at 128 x 64 (the one-tile x1 pass measured slower that way, 581
+        // -> 647); so do the persistent y1 and x1 passes, with their addresses
+        // kept in registers and the next tile's loads issued in parts (256 x 128
+        // y1: 4.28 -> 3.83 ms; 128 x 96 x1: 0.559 -> 0.526 ms).
         int64_t w = axis3_nominal_w(axis, p.n, t3, nst, mixed);
         w = std::min<int64_t>(w, ilog2_pow2_divisor(p.nlines));
         if (axis == AX_X2) w = std::min<int64_t>(w, ilog2_pow2_divisor(ny));

@@ -92,8 +92,8 @@ __host__ __device__ constexpr int axis3_block_threads(int axis, int n, int nst, 
 __host__ __device__ constexpr int axis3_nominal_w(int axis, int n, int t3, int nst, bool mixed) {
     const int bt = axis3_block_threads(axis, n, nst, mixed);
     const bool wide = n != 128;
-    // the complex64 x2 and (persistent) y1 passes of 128-point lines: 32 lines
-    const bool c64_32 = n == 128 && nst == 1 && mixed && (axis == AX_X2 || axis == AX_Y1);
+    // the complex64 x2 and (persistent) x1 and y1 passes of 128-point lines: 32 lines
+    const bool c64_32 = n == 128 && nst == 1 && mixed && (axis == AX_X2 || axis == AX_Y1 || axis == AX_X1);
     int w = (bt == 1024 ? 1024 : (wide || c64_32) ? 512 : 256) / t3;
     const int cap = (bt == 1024 || c64_32) ? (81920 - 2 * n * 16) / (n * 8) - 1
                   : nst == 1 ? ((wide ? 81920 : 49152) - 2 * n * 16) / (n * 16) - 1
