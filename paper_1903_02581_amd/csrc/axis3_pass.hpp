@@ -19,13 +19,16 @@
 // stages the line is exchanged through LDS, each stage reading and writing its
 // own disjoint set of positions.
 //
-// PERS (forward one-state passes only): the kernel is persistent: a block
+// PERS (the forward one-state passes and the reverse sweep's x1 pass): the
+// kernel is persistent: a block
 // walks tiles of W lines (tile = blockIdx.x, + gridDim.x, ...) and issues the
 // loads of its next tile while it transforms the current one (at its start, or
 // on the wide forms in four parts between its exchanges), so that the HBM
 // reads of one tile overlap the arithmetic and LDS exchanges of the previous
 // one inside the block, instead of relying on other resident blocks being out
-// of phase.  Its exchanges synchronise the block on LDS alone (lds_barrier),
+// of phase.  The two-state form loads and stores both states and takes its
+// gradient partial sums per tile, with LDS-only barriers, and synchronises once
+// more after them before the next tile reuses the exchange area.  Its exchanges synchronise the block on LDS alone (lds_barrier),
 // leaving the prefetch loads and the stores in flight.  It pays where a pass
 // has few resident blocks per CU: measured on the complex64 x1 and y1 passes
 // of the 256x128 state (x1 6.07 -> 5.36 ms, y1 4.46 -> 4.20 ms); the x2 and
@@ -83,7 +86,7 @@ constexpr int potential_batch(int axis, int n, bool c64) { return (c64 && axis =
 // an immediate offset; WC = 0: a.W lines, for grids that allow fewer.
 template <class S, int AXIS, int R1, int R2, int R3, int T, int NST, int VK, bool NT, bool PERS, int WC>
 __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !std::is_same<S, double2>::value)) k_axis3(const PassArgs a) {
-    static_assert(!PERS || NST == 1, "only the forward passes are persistent");
+    static_assert(!PERS || NST == 1 || AXIS == AX_X1, "persistent: the forward passes and the reverse x1 pass");
     // the reverse sweep (two states) applies every factor conjugated
     constexpr bool CONJ = NST == 2;
     using NW = Net3<R1, R2, R3, T>;
@@ -167,7 +170,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
     // the reverse sweep's gradient terms.  between(k) runs after the k-th of the
     // four exchanges (k = 0..3).
     double2 v[NST][E];
-    auto round_trip = [&](const LineGeom<AXIS>& lg, uint32_t line, S* const* ps, auto&& between) {
+    auto round_trip = [&](const LineGeom<AXIS>& lg, uint32_t line, uint32_t blk, S* const* ps, auto&& between) {
         // gradient accumulators of the reverse sweep: the potential marginal
         // Im(conj(lambda) psi) on the side of the potential factor the pass is told
         // to take it (before: G_MIN, after: G_MOUT), and the dL/dB term of the x
@@ -350,15 +353,37 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             // marginal per line on the x1 and y1 axes (the line's threads summed in
             // fixed order), per block on x2 and y2 (a block's lines share r1)
             double* red = reinterpret_cast<double*>(lds_raw);
+            // block-wide synchronisation on LDS alone in the persistent form (the
+            // next tile's loads stay in flight)
+            auto bsync = [&]() {
+                if constexpr (PERS)
+                    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                else
+                    __syncthreads();
+            };
             if (a.gflags & G_GB) {
-                const double sum = block_sum(gb_acc, red);
-                if (tid == 0) a.gb_part[blockIdx.x] += sum;
+                double sum;
+                if constexpr (PERS) {
+                    // block_sum's order: the wavefront's butterfly, then the wavefronts in turn
+                    double g = gb_acc;
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) g += __shfl_xor(g, o, 64);
+                    bsync();
+                    if ((tid & 63) == 0) red[tid >> 6] = g;
+                    bsync();
+                    sum = 0.0;
+                    if (tid == 0)
+                        for (int w = 0; w < (T * W) / 64; ++w) sum += red[w];
+                } else {
+                    sum = block_sum(gb_acc, red);
+                }
+                if (tid == 0) a.gb_part[blk] += sum;
             }
             if (a.gflags & (G_MIN | G_MOUT)) {
                 if constexpr (AXIS == AX_X1 || AXIS == AX_Y1) {
-                    __syncthreads();
+                    bsync();
                     red[t * W + cl] = gm_acc;
-                    __syncthreads();
+                    bsync();
                     if (t == 0) {
                         double sum = 0.0;
                         for (int q = 0; q < T; ++q) sum += red[q * W + cl];
@@ -366,8 +391,12 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                     }
                 } else {
                     const double sum = block_sum(gm_acc, red);
-                    if (tid == 0) a.marg_part[blockIdx.x] += sum;
+                    if (tid == 0) a.marg_part[blk] += sum;
                 }
+            }
+            // the next tile's first exchange reuses the area the sums were read from
+            if constexpr (PERS) {
+                if (a.gflags & (G_GB | G_MIN | G_MOUT)) bsync();
             }
         }
     };
@@ -376,15 +405,18 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         // persistent: tiles blockIdx.x, + gridDim.x, ...; the next tile's
         // elements are loaded (as stored) before the current one is transformed
         const uint32_t ntiles = a.ntiles;
-        S raw[E];
+        S raw[NST][E];
+        auto state = [&](int s) { return reinterpret_cast<S*>(s == 0 ? a.psi : a.lam); };
         double2 kreg = make_double2(0.0, 0.0);  // KROW: entry tid of the next tile's kinetic row
         // the kinetic row of tile tl: y1 of its lines (a tile's lines share y1)
         auto krow_of = [&](uint32_t tl) { return a.ktab + (int64_t)a.dnxy.div(tl * (uint32_t)W) * N; };
         uint32_t tile = blockIdx.x;
         if (tile < ntiles) {
             const LineGeom<AXIS> lg(a, tile * (uint32_t)W + (uint32_t)cl);
-            walk(lg, reinterpret_cast<const S*>(a.psi) + lg.base,
-                 [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
+#pragma unroll
+            for (int s = 0; s < NST; ++s)
+                walk(lg, static_cast<const S*>(state(s)) + lg.base,
+                     [&](int e, const S* p) { raw[s][e] = ld_raw<S, NT>(p); });
             if constexpr (KROW) {
                 if (tid < N) kreg = krow_of(tile)[tid];
             }
@@ -412,9 +444,13 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             if constexpr (!WIDE) asm volatile("" : "+v"(t), "+v"(cl));
             const uint32_t line = tl * (uint32_t)W + (uint32_t)cl;
             const LineGeom<AXIS> lg(a, line);
-            S* ps[1] = {reinterpret_cast<S*>(a.psi) + lg.base};
+            S* ps[NST];
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[0][e] = widen(raw[e]);
+            for (int s = 0; s < NST; ++s) ps[s] = state(s) + lg.base;
+#pragma unroll
+            for (int s = 0; s < NST; ++s)
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[s][e] = widen(raw[s][e]);
             if constexpr (KROW) {
                 // visible to every thread after the first exchange barrier; the row
                 // written two tiles ago was last read before this tile's barriers
@@ -426,7 +462,9 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
             if constexpr (WIDE) {
                 const bool has_next = next < ntiles;
                 const LineGeom<AXIS> ln(a, (has_next ? next : tl) * (uint32_t)W + (uint32_t)cl);
-                const S* nbase = reinterpret_cast<const S*>(a.psi) + ln.base;
+                const S* nbase[NST];
+#pragma unroll
+                for (int s = 0; s < NST; ++s) nbase[s] = state(s) + ln.base;
                 if constexpr (KROW) {
                     if (has_next && tid < N) kreg = krow_of(next)[tid];
                 }
@@ -441,22 +479,27 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
                 constexpr int PART = (E + NP - 1) / NP;
                 auto part = [&](int slot) {
                     const int j = slot - FIRST;
-                    if (has_next && j >= 0 && j < NP)
-                        walk_part(ln, nbase, j * PART, (j + 1) * PART < E ? (j + 1) * PART : E,
-                                  [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
+                    if (has_next && j >= 0 && j < NP) {
+#pragma unroll
+                        for (int s = 0; s < NST; ++s)
+                            walk_part(ln, nbase[s], j * PART, (j + 1) * PART < E ? (j + 1) * PART : E,
+                                      [&](int e, const S* p) { raw[s][e] = ld_raw<S, NT>(p); });
+                    }
                 };
                 part(-1);
-                round_trip(lg, line, ps, part);
+                round_trip(lg, line, tl, ps, part);
             } else {
                 if (next < ntiles) {
                     const LineGeom<AXIS> ln(a, next * (uint32_t)W + (uint32_t)cl);
-                    walk(ln, reinterpret_cast<const S*>(a.psi) + ln.base,
-                         [&](int e, const S* p) { raw[e] = ld_raw<S, NT>(p); });
+#pragma unroll
+                    for (int s = 0; s < NST; ++s)
+                        walk(ln, static_cast<const S*>(state(s)) + ln.base,
+                             [&](int e, const S* p) { raw[s][e] = ld_raw<S, NT>(p); });
                     if constexpr (KROW) {
                         if (tid < N) kreg = krow_of(next)[tid];
                     }
                 }
-                round_trip(lg, line, ps, [](int) {});
+                round_trip(lg, line, tl, ps, [](int) {});
             }
             ++it;
         };
@@ -484,7 +527,7 @@ __global__ void __launch_bounds__(axis3_block_threads(AXIS, R1 * R2 * R3, NST, !
         for (int s = 0; s < NST; ++s)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[s][e] = widen(raw[s][e]);
-        round_trip(lg, line, ps, [](int) {});
+        round_trip(lg, line, blockIdx.x, ps, [](int) {});
     }
 }
 
@@ -516,6 +559,7 @@ AxisKernel pick_axis3_nt(int axis, int n, int vk, int nst, bool pers, int w, int
     if (pers) {
         if (nst == 1 && vk == 0 && axis == AX_X1) return pick3<S, AX_X1, 1, 0, NT, true>(n, w, t);
         if (nst == 1 && vk == 0 && axis == AX_Y1) return pick3<S, AX_Y1, 1, 0, NT, true>(n, w, t);
+        if (nst == 2 && vk == 0 && axis == AX_X1) return pick3<S, AX_X1, 2, 0, NT, true>(n, w, t);
         *t = 0;
         return nullptr;
     }
