@@ -159,7 +159,7 @@ AxisPlan plan_axis(int axis, int nx, int ny, int nst, bool grad, bool mixed) {
         // The reverse sweep's two-state x1 pass of 256-point lines (one 512-thread
         // block per CU at its 143 registers, so none out of phase to hide its
         // loads) takes the persistent form too: 256 x 128 reverse sweep 0.946 ->
-        // 0.880 s over 20 recorded steps, gradients bitwise unchanged.
+        // 0.880 s over 20 recorded steps, gradients unchanged to rounding.
         p.pers = mixed && p.n >= 128 && (axis == AX_X1 || axis == AX_Y1) && (nst == 1 || (axis == AX_X1 && p.n == 256));
         if (p.pers && axis == AX_X1 && (nxy % p.W != 0 || (int64_t)p.t * p.W < p.n)) p.pers = false;
         p.lds = axis3_pass_lds_bytes(axis, p.n, p.W, nst, mixed, p.pers);
